@@ -1,0 +1,163 @@
+/*
+ * gridbuild.h - C ABI of the MI355X (gfx950) parallel uniform-grid builder.
+ *
+ * The library implements BuildParallelGrid (Algorithm 1 of Costa, Pereira and
+ * Jorge, "Building An Efficient Grid On GPU"): for every triangle it counts the
+ * grid cells its bounding box overlaps (CountCells), turns the counts into
+ * one work item per <object, cell> pair with an exclusive scan (ExclusiveSum,
+ * MakeObjectIds, InclusiveSum, SegmentedExclusiveSum), maps each item to its
+ * global cell (GlobalCoords, MakeCellIds), sorts the pairs by cell with an LSD
+ * radix sort (RadixSort) and extracts each cell's slice of the sorted list
+ * (RunLengthEncode, NonEmptyCells, ExclusiveSum over the grid).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Device pointers point to memory the caller owns (e.g. PyTorch tensors);
+ *    the library never allocates or frees device memory.  Host pointers are
+ *    marked "host".  Scratch memory is passed in as a workspace (ws, ws_bytes)
+ *    whose required size the *_workspace_size functions report.
+ *  - stream is a hipStream_t (NULL = the default stream).  All device work is
+ *    ordered on it.  Entry points that must read a result back (the pair count)
+ *    synchronize that stream once and say so.
+ *  - Inputs: verts_soa is FP32 [3][nverts] (all x, then all y, then all z);
+ *    tris is uint32 [ntris][3] vertex indices.  lo, hi (host, 3 floats) are the
+ *    grid bounds and res (host, 3 uint32) the cells per axis.
+ *  - Grid contract (the paper leaves these open; this is the library's reading):
+ *      inv[a]  = (float)res[a] / (hi[a] - lo[a])      FP32, on the host
+ *      cell(p) = min(max(floor((p - lo) * inv), 0), res - 1)   FP32, no FMA
+ *      a triangle's box on axis a = [cell(min p), cell(max p)]  (IEEE minNum/
+ *      maxNum over its three vertices), cell id = x + rx * (y + ry * z).
+ *    Points outside the bounds are clamped onto the boundary cells; NaN maps to
+ *    cell 0.  Every triangle therefore covers at least one cell.
+ *  - Outputs (grid_out): cells[i], objs[i] for i < npairs are the pairs sorted
+ *    by cell and, within a cell, by ascending object id (a stable sort of the
+ *    object-order list; the result is unique).  ranges is uint32 [2 * R]
+ *    (R = rx * ry * rz) with ranges[2c] = number of pairs whose cell is < c and
+ *    ranges[2c + 1] = number whose cell is <= c, so cell c owns
+ *    objs[ranges[2c] .. ranges[2c + 1]) and an empty cell has an empty range.
+ *    This is the paper's compact grid G (the begin column) plus each end.
+ *  - Return value: GRID_OK or a negative grid_status.  On error the outputs'
+ *    contents are unspecified, except that GRID_E_CAPACITY still reports the
+ *    required pair count.  No exception or abort crosses the ABI.
+ *  - Limits: 1 <= res[a] <= 1024; NO (the pair count) <= 2^32 - 1; ntris < 2^31.
+ *  - Thread safety: calls on different workspaces may run concurrently;
+ *    calls sharing one workspace must be ordered (same stream or synchronized).
+ */
+#ifndef GRIDBUILD_H
+#define GRIDBUILD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum grid_status {
+  GRID_OK = 0,
+  GRID_E_INVAL = -1,     /* null pointer, res outside [1, 1024], !(lo < hi), non-finite bounds */
+  GRID_E_NOMEM = -2,     /* workspace smaller than the size the library asked for */
+  GRID_E_OVERFLOW = -3,  /* NO > 2^32 - 1 */
+  GRID_E_CAPACITY = -4,  /* NO > cap_pairs; npairs holds the required count */
+  GRID_E_BADINDEX = -5,  /* a triangle references a vertex index >= nverts */
+  GRID_E_HIP = -6        /* a HIP runtime call failed */
+} grid_status;
+
+/* Output of one grid.  cells/objs/ranges are device pointers owned by the caller. */
+typedef struct grid_out {
+  uint32_t *cells;     /* [cap_pairs] sorted cell ids                          */
+  uint32_t *objs;      /* [cap_pairs] object ids, ascending within each cell    */
+  uint32_t *ranges;    /* [2 * R] (begin, end) per cell, x-fastest cell order   */
+  uint64_t cap_pairs;  /* in: capacity of cells/objs, in pairs                  */
+  uint64_t npairs;     /* out: NO, the number of <obj, cell> pairs              */
+} grid_out;
+
+/* One grid of a batch: the same arguments as grid_build, plus its outputs. */
+typedef struct grid_desc {
+  const float *verts_soa;  /* device, FP32 [3][nverts] */
+  const uint32_t *tris;    /* device, uint32 [ntris][3] */
+  uint32_t nverts;
+  uint32_t ntris;
+  float lo[3];
+  float hi[3];
+  uint32_t res[3];
+  grid_out out;
+} grid_desc;
+
+/* Human-readable name of a status code (static storage). */
+const char *grid_strerror(int status);
+
+/* Bytes of workspace grid_count / grid_build / grid_expand need for a grid of
+ * ntris triangles, at most cap_pairs pairs and res cells (host array). */
+size_t grid_workspace_size(uint32_t ntris, uint64_t cap_pairs, const uint32_t res[3]);
+
+/* CountCells + ExclusiveSum (Algorithm 1, first two steps; Section 3 text).
+ * Writes *npairs (host) = NO.  If start_out (device, uint32 [ntris]) is not
+ * NULL it receives each triangle's exclusive pair offset, so its cell count is
+ * start[t+1] - start[t] (NO - start[T-1] for the last).  Synchronizes stream. */
+int grid_count(const float *verts_soa, uint32_t nverts, const uint32_t *tris, uint32_t ntris,
+               const float lo[3], const float hi[3], const uint32_t res[3],
+               void *ws, size_t ws_bytes, uint32_t *start_out, uint64_t *npairs, void *stream);
+
+/* The whole build, BuildParallelGrid(M, boxes) -> (G, O) (Algorithm 1), into
+ * out (cells, objs: cap_pairs entries; ranges: 2 * R entries).  Synchronizes
+ * stream once, after the count, to size the pair list (the paper allocates O and
+ * C from NO at that point); the rest is left ordered on stream. */
+int grid_build(const float *verts_soa, uint32_t nverts, const uint32_t *tris, uint32_t ntris,
+               const float lo[3], const float hi[3], const uint32_t res[3],
+               void *ws, size_t ws_bytes, grid_out *out, void *stream);
+
+/* Object-order pair lists (Algorithm 1, MakeObjectIds through MakeCellIds;
+ * Section 3 and GlobalCoords): cells[i], objs[i] for i < NO in object order,
+ * each object's cells in GlobalCoords order (x fastest).  Device outputs of
+ * cap_pairs entries; *npairs (host) = NO.  Synchronizes stream. */
+int grid_expand(const float *verts_soa, uint32_t nverts, const uint32_t *tris, uint32_t ntris,
+                const float lo[3], const float hi[3], const uint32_t res[3],
+                void *ws, size_t ws_bytes, uint32_t *cells, uint32_t *objs, uint64_t cap_pairs,
+                uint64_t *npairs, void *stream);
+
+/* Batched builds: ngrids independent grids (host array of descriptors) built
+ * in one fixed sequence of launches.  Every grid's outputs are identical to
+ * what grid_build returns for it alone: object ids local to the grid, ranges
+ * relative to the grid's own pair list.  Pairs are sorted on a packed key
+ * (grid index above the cell id) over only the bits in use. */
+size_t grid_workspace_size_batched(const grid_desc *grids, uint32_t ngrids);
+
+/* Per-grid NO into grids[g].out.npairs (host).  Synchronizes stream. */
+int grid_count_batched(grid_desc *grids, uint32_t ngrids, void *ws, size_t ws_bytes, void *stream);
+
+/* Build all grids; writes grids[g].out.npairs.  If any grid's NO exceeds its
+ * cap_pairs the call returns GRID_E_CAPACITY after the count (every npairs is
+ * then set) and builds nothing.  Synchronizes stream once, after the count. */
+int grid_build_batched(grid_desc *grids, uint32_t ngrids, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- building blocks, exposed for testing and reuse ------------------------ */
+
+/* Stable LSD radix sort of (keys, vals) by the low nbits bits of keys
+ * (0 <= nbits <= 32; higher key bits must be zero).  keys_alt/vals_alt are
+ * device buffers of n entries used as the other half of the double buffer; the
+ * result is left in keys/vals.  The sort step of Algorithm 1 (RadixSort). */
+size_t grid_sort_workspace_size(uint64_t n, uint32_t nbits);
+int grid_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                    uint64_t n, uint32_t nbits, void *ws, size_t ws_bytes, void *stream);
+
+/* Single-pass scans over uint32 device arrays (decoupled look-back):
+ *  GRID_SCAN_EXCLUSIVE_SUM   out[i] = in[0] + ... + in[i-1] (mod 2^32);
+ *                            *total (host) = full sum in 64 bits
+ *  GRID_SCAN_INCLUSIVE_MAX   out[i] = max(in[0..i]);   *total = max
+ *  GRID_SCAN_SEGMENTED_EXCLUSIVE_SUM  as the exclusive sum, restarting at 0
+ *                            wherever flags[i] != 0 (flags: device uint32 [n]);
+ *                            *total = sum of the last segment
+ * These are the ExclusiveSum / InclusiveSum / SegmentedExclusiveSum steps of
+ * Algorithm 1 (the inclusive scan in its max form, which the library uses to
+ * spread object ids over their pair slots).  Synchronizes stream. */
+enum { GRID_SCAN_EXCLUSIVE_SUM = 0, GRID_SCAN_INCLUSIVE_MAX = 1, GRID_SCAN_SEGMENTED_EXCLUSIVE_SUM = 2 };
+size_t grid_scan_workspace_size(uint64_t n);
+int grid_scan_u32(const uint32_t *in, const uint32_t *flags, uint32_t *out, uint64_t n, int op,
+                  void *ws, size_t ws_bytes, uint64_t *total, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRIDBUILD_H */

@@ -1,0 +1,326 @@
+"""ctypes binding of libgridbuild.so (the C ABI declared in include/gridbuild.h).
+
+Argument marshalling only: PyTorch provides device memory and the stream, and
+every step of the build runs in the library's HIP kernels.  There is no other
+code path: if the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+import threading
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch  # must be imported before the library so both share one HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgridbuild.so")
+
+GRID_OK = 0
+GRID_E_INVAL = -1
+GRID_E_NOMEM = -2
+GRID_E_OVERFLOW = -3
+GRID_E_CAPACITY = -4
+GRID_E_BADINDEX = -5
+GRID_E_HIP = -6
+
+SCAN_EXCLUSIVE_SUM = 0
+SCAN_INCLUSIVE_MAX = 1
+SCAN_SEGMENTED_EXCLUSIVE_SUM = 2
+
+EXPORTS = (
+    "grid_strerror", "grid_workspace_size", "grid_count", "grid_build", "grid_expand",
+    "grid_workspace_size_batched", "grid_count_batched", "grid_build_batched",
+    "grid_sort_workspace_size", "grid_sort_pairs", "grid_scan_workspace_size", "grid_scan_u32",
+)
+
+
+class GridError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = lib().grid_strerror(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{what}: {msg} (status {status})" if what else f"{msg} (status {status})")
+
+
+class grid_out(C.Structure):
+    _fields_ = [("cells", C.c_void_p), ("objs", C.c_void_p), ("ranges", C.c_void_p),
+                ("cap_pairs", C.c_uint64), ("npairs", C.c_uint64)]
+
+
+class grid_desc(C.Structure):
+    _fields_ = [("verts_soa", C.c_void_p), ("tris", C.c_void_p), ("nverts", C.c_uint32), ("ntris", C.c_uint32),
+                ("lo", C.c_float * 3), ("hi", C.c_float * 3), ("res", C.c_uint32 * 3), ("out", grid_out)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """Load libgridbuild.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2403_10647_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P, U32, U64, SZ = C.c_void_p, C.c_uint32, C.c_uint64, C.c_size_t
+        F3, U3 = C.POINTER(C.c_float), C.POINTER(C.c_uint32)
+        L.grid_strerror.argtypes = [C.c_int]
+        L.grid_strerror.restype = C.c_char_p
+        L.grid_workspace_size.argtypes = [U32, U64, U3]
+        L.grid_workspace_size.restype = SZ
+        L.grid_count.argtypes = [P, U32, P, U32, F3, F3, U3, P, SZ, P, C.POINTER(C.c_uint64), P]
+        L.grid_build.argtypes = [P, U32, P, U32, F3, F3, U3, P, SZ, C.POINTER(grid_out), P]
+        L.grid_expand.argtypes = [P, U32, P, U32, F3, F3, U3, P, SZ, P, P, U64, C.POINTER(C.c_uint64), P]
+        L.grid_workspace_size_batched.argtypes = [C.POINTER(grid_desc), U32]
+        L.grid_workspace_size_batched.restype = SZ
+        L.grid_count_batched.argtypes = [C.POINTER(grid_desc), U32, P, SZ, P]
+        L.grid_build_batched.argtypes = [C.POINTER(grid_desc), U32, P, SZ, P]
+        L.grid_sort_workspace_size.argtypes = [U64, U32]
+        L.grid_sort_workspace_size.restype = SZ
+        L.grid_sort_pairs.argtypes = [P, P, P, P, U64, U32, P, SZ, P]
+        L.grid_scan_workspace_size.argtypes = [U64]
+        L.grid_scan_workspace_size.restype = SZ
+        L.grid_scan_u32.argtypes = [P, P, P, U64, C.c_int, P, SZ, C.POINTER(C.c_uint64), P]
+        for name in ("grid_count", "grid_build", "grid_expand", "grid_count_batched", "grid_build_batched",
+                     "grid_sort_pairs", "grid_scan_u32"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+        return _lib
+
+
+def _check(st: int, what: str):
+    if st != GRID_OK:
+        raise GridError(st, what)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _f3(x):
+    return (C.c_float * 3)(*[float(v) for v in x])
+
+
+def _u3(x):
+    return (C.c_uint32 * 3)(*[int(v) for v in x])
+
+
+class Workspace:
+    """A growable device byte buffer (a torch tensor) handed to the library."""
+
+    def __init__(self, device="cuda"):
+        self.device = torch.device(device)
+        self.buf: Optional[torch.Tensor] = None
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+    def ptr_size(self, nbytes: int):
+        b = self.get(nbytes)
+        return C.c_void_p(b.data_ptr()), C.c_size_t(b.numel())
+
+
+_default_ws = {}
+
+
+def default_workspace(device=None) -> Workspace:
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    key = (dev.type, dev.index)
+    if key not in _default_ws:
+        _default_ws[key] = Workspace(dev)
+    return _default_ws[key]
+
+
+@dataclasses.dataclass
+class GridInput:
+    """Device-resident grid request: verts FP32 [3, V], tris int32 [T, 3]."""
+    verts: torch.Tensor
+    tris: torch.Tensor
+    lo: Sequence[float]
+    hi: Sequence[float]
+    res: Sequence[int]
+
+    @property
+    def ntris(self) -> int:
+        return int(self.tris.shape[0])
+
+    @property
+    def nverts(self) -> int:
+        return int(self.verts.shape[1])
+
+    @property
+    def ncells(self) -> int:
+        return int(np.prod(np.asarray(self.res, np.int64)))
+
+    @staticmethod
+    def from_scene(scene, device="cuda") -> "GridInput":
+        v = torch.from_numpy(np.ascontiguousarray(scene.verts, np.float32)).to(device)
+        t = torch.from_numpy(np.ascontiguousarray(scene.tris).view(np.int32)).to(device)
+        return GridInput(v, t, list(map(float, scene.lo)), list(map(float, scene.hi)), list(map(int, scene.res)))
+
+
+@dataclasses.dataclass
+class GridResult:
+    cells: torch.Tensor      # int32 view of uint32 [npairs]
+    objs: torch.Tensor       # int32 view of uint32 [npairs]
+    ranges: torch.Tensor     # int32 view of uint32 [2R]
+    npairs: int
+
+    def numpy(self):
+        c = self.cells[: self.npairs].cpu().numpy().view(np.uint32)
+        o = self.objs[: self.npairs].cpu().numpy().view(np.uint32)
+        r = self.ranges.cpu().numpy().view(np.uint32)
+        return c, o, r
+
+
+def _input_args(g: GridInput):
+    assert g.verts.dtype == torch.float32 and g.verts.is_contiguous() and g.verts.dim() == 2 and g.verts.shape[0] == 3
+    assert g.tris.dtype == torch.int32 and g.tris.is_contiguous() and (g.tris.numel() == 0 or g.tris.shape[1] == 3)
+    return (C.c_void_p(g.verts.data_ptr()), C.c_uint32(g.nverts), C.c_void_p(g.tris.data_ptr()),
+            C.c_uint32(g.ntris), _f3(g.lo), _f3(g.hi), _u3(g.res))
+
+
+def workspace_size(ntris: int, cap_pairs: int, res) -> int:
+    return int(lib().grid_workspace_size(ntris, cap_pairs, _u3(res)))
+
+
+def count(g: GridInput, ws: Optional[Workspace] = None, with_start: bool = False, stream=None):
+    """CountCells + ExclusiveSum: (NO, start[T] or None)."""
+    L = lib()
+    ws = ws or default_workspace(g.verts.device)
+    wp, wn = ws.ptr_size(workspace_size(g.ntris, 0, g.res))
+    start = torch.empty(max(g.ntris, 1), dtype=torch.int32, device=g.verts.device) if with_start else None
+    no = C.c_uint64(0)
+    st = L.grid_count(*_input_args(g), wp, wn, C.c_void_p(start.data_ptr()) if start is not None else None,
+                      C.byref(no), _stream(stream))
+    _check(st, "grid_count")
+    return int(no.value), (start[: g.ntris] if start is not None else None)
+
+
+def build(g: GridInput, cap_pairs: Optional[int] = None, ws: Optional[Workspace] = None, out: Optional[GridResult] = None,
+          stream=None) -> GridResult:
+    """The whole build.  With no capacity given, counts first to size the outputs."""
+    L = lib()
+    ws = ws or default_workspace(g.verts.device)
+    if out is None:
+        if cap_pairs is None:
+            cap_pairs, _ = count(g, ws, stream=stream)
+        dev = g.verts.device
+        out = GridResult(torch.empty(max(cap_pairs, 1), dtype=torch.int32, device=dev),
+                         torch.empty(max(cap_pairs, 1), dtype=torch.int32, device=dev),
+                         torch.empty(2 * g.ncells, dtype=torch.int32, device=dev), 0)
+    cap = int(out.cells.numel()) if cap_pairs is None else int(cap_pairs)
+    wp, wn = ws.ptr_size(workspace_size(g.ntris, cap, g.res))
+    o = grid_out(out.cells.data_ptr(), out.objs.data_ptr(), out.ranges.data_ptr(), cap, 0)
+    st = L.grid_build(*_input_args(g), wp, wn, C.byref(o), _stream(stream))
+    out.npairs = int(o.npairs)
+    _check(st, "grid_build")
+    return out
+
+
+def expand(g: GridInput, ws: Optional[Workspace] = None, stream=None):
+    """Object-order (cells, objs) lists."""
+    L = lib()
+    ws = ws or default_workspace(g.verts.device)
+    no, _ = count(g, ws, stream=stream)
+    dev = g.verts.device
+    cells = torch.empty(max(no, 1), dtype=torch.int32, device=dev)
+    objs = torch.empty(max(no, 1), dtype=torch.int32, device=dev)
+    wp, wn = ws.ptr_size(workspace_size(g.ntris, no, g.res))
+    n = C.c_uint64(0)
+    st = L.grid_expand(*_input_args(g), wp, wn, C.c_void_p(cells.data_ptr()), C.c_void_p(objs.data_ptr()), no,
+                       C.byref(n), _stream(stream))
+    _check(st, "grid_expand")
+    return cells[:no], objs[:no]
+
+
+def _descs(inputs: List[GridInput], outs: Optional[List[GridResult]] = None):
+    arr = (grid_desc * len(inputs))()
+    for i, g in enumerate(inputs):
+        d = arr[i]
+        d.verts_soa = g.verts.data_ptr()
+        d.tris = g.tris.data_ptr()
+        d.nverts = g.nverts
+        d.ntris = g.ntris
+        d.lo[:] = [float(x) for x in g.lo]
+        d.hi[:] = [float(x) for x in g.hi]
+        d.res[:] = [int(x) for x in g.res]
+        if outs is not None:
+            o = outs[i]
+            d.out.cells = o.cells.data_ptr()
+            d.out.objs = o.objs.data_ptr()
+            d.out.ranges = o.ranges.data_ptr()
+            d.out.cap_pairs = int(o.cells.numel())
+    return arr
+
+
+def count_batched(inputs: List[GridInput], ws: Optional[Workspace] = None, stream=None) -> List[int]:
+    L = lib()
+    ws = ws or default_workspace(inputs[0].verts.device)
+    arr = _descs(inputs)
+    wp, wn = ws.ptr_size(L.grid_workspace_size_batched(arr, len(inputs)))
+    st = L.grid_count_batched(arr, len(inputs), wp, wn, _stream(stream))
+    _check(st, "grid_count_batched")
+    return [int(arr[i].out.npairs) for i in range(len(inputs))]
+
+
+def alloc_results(inputs: List[GridInput], caps: List[int]) -> List[GridResult]:
+    dev = inputs[0].verts.device
+    return [GridResult(torch.empty(max(c, 1), dtype=torch.int32, device=dev),
+                       torch.empty(max(c, 1), dtype=torch.int32, device=dev),
+                       torch.empty(2 * g.ncells, dtype=torch.int32, device=dev), 0)
+            for g, c in zip(inputs, caps)]
+
+
+def build_batched(inputs: List[GridInput], outs: Optional[List[GridResult]] = None, ws: Optional[Workspace] = None,
+                  stream=None) -> List[GridResult]:
+    L = lib()
+    ws = ws or default_workspace(inputs[0].verts.device)
+    if outs is None:
+        outs = alloc_results(inputs, count_batched(inputs, ws, stream))
+    arr = _descs(inputs, outs)
+    wp, wn = ws.ptr_size(L.grid_workspace_size_batched(arr, len(inputs)))
+    st = L.grid_build_batched(arr, len(inputs), wp, wn, _stream(stream))
+    for i, o in enumerate(outs):
+        o.npairs = int(arr[i].out.npairs)
+    _check(st, "grid_build_batched")
+    return outs
+
+
+def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, nbits: int, ws: Optional[Workspace] = None, stream=None):
+    """Stable radix sort of int32-viewed uint32 (keys, vals) in place by the low nbits bits."""
+    L = lib()
+    n = keys.numel()
+    ws = ws or default_workspace(keys.device)
+    ka = torch.empty_like(keys)
+    va = torch.empty_like(vals)
+    wp, wn = ws.ptr_size(L.grid_sort_workspace_size(n, nbits))
+    st = L.grid_sort_pairs(C.c_void_p(keys.data_ptr()), C.c_void_p(vals.data_ptr()), C.c_void_p(ka.data_ptr()),
+                           C.c_void_p(va.data_ptr()), n, nbits, wp, wn, _stream(stream))
+    _check(st, "grid_sort_pairs")
+    return keys, vals
+
+
+def scan_u32(x: torch.Tensor, op: int, flags: Optional[torch.Tensor] = None, ws: Optional[Workspace] = None,
+             stream=None):
+    L = lib()
+    n = x.numel()
+    ws = ws or default_workspace(x.device)
+    out = torch.empty_like(x)
+    tot = C.c_uint64(0)
+    wp, wn = ws.ptr_size(L.grid_scan_workspace_size(n))
+    st = L.grid_scan_u32(C.c_void_p(x.data_ptr()), C.c_void_p(flags.data_ptr()) if flags is not None else None,
+                         C.c_void_p(out.data_ptr()), n, op, wp, wn, C.byref(tot), _stream(stream))
+    _check(st, "grid_scan_u32")
+    return out, int(tot.value)

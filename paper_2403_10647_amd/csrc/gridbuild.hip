@@ -1,0 +1,773 @@
+// Host side of the gfx950 grid builder: argument checks, workspace layout,
+// the radix-sort plan and the launch sequence behind the C ABI of gridbuild.h.
+#include "../../include/gridbuild.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "kernels.hpp"
+#include "ranges.hpp"
+#include "scan.hpp"
+#include "sort.hpp"
+
+using namespace gb;
+
+namespace {
+
+// ---- launch shapes ----------------------------------------------------------
+constexpr int kCountBlock = 256, kCountK = 8;           // 2048 triangles per count tile
+constexpr int kSortBlock = 512, kSortK = 16;            // 8192 pairs per sort tile
+constexpr int kSortTile = kSortBlock * kSortK;
+constexpr int kSortTileShift = 13;
+constexpr int kRangesBlock = 256, kRangesK = 16;        // 4096 merge items per range tile
+constexpr int kMergeTile = kRangesBlock * kRangesK;
+constexpr int kScanBlock = 256, kScanK = 8;
+constexpr int kPlanBlock = 1024;
+constexpr int kMaxRadixBits = 11;
+static_assert((1 << kSortTileShift) == kSortTile, "sort tile must be a power of two");
+
+#define GB_TRY(expr)                             \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return GRID_E_HIP;     \
+  } while (0)
+#define GB_LAUNCHED() GB_TRY(hipGetLastError())
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+uint32_t bits_for(uint64_t n) {  // smallest b with 2^b >= n
+  uint32_t b = 0;
+  while ((uint64_t{1} << b) < n) ++b;
+  return b;
+}
+
+int device_cus() {
+  static std::mutex mu;
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  std::lock_guard<std::mutex> lock(mu);
+  if (cache[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cache[dev] = n;
+  }
+  return cache[dev];
+}
+
+// ---- radix-sort plan ----------------------------------------------------------
+struct Plan {
+  SortPlan sp;
+  int rb;  // template radix bits (8..11)
+};
+
+int g_max_digit_bits = 9;  // tunable: widest digit a pass may use
+
+Plan make_plan(uint32_t bits, int max_digit = -1) {
+  Plan p{};
+  const int md = std::min(kMaxRadixBits, std::max(4, max_digit > 0 ? max_digit : g_max_digit_bits));
+  if (bits == 0) {
+    p.sp.passes = 0;
+    p.rb = 8;
+    return p;
+  }
+  const uint32_t passes = (bits + md - 1) / md;
+  const uint32_t w = (bits + passes - 1) / passes;
+  p.sp.passes = passes;
+  for (uint32_t i = 0; i < passes; ++i) {
+    p.sp.shift[i] = i * w;
+    p.sp.width[i] = std::min(w, bits - i * w);
+  }
+  p.rb = std::max(8, static_cast<int>(w));
+  return p;
+}
+
+// ---- workspace layout -----------------------------------------------------------
+struct Layout {
+  size_t ctl, hist, count_status, zero_end;
+  size_t start, box, tfo, sort_status, keys_alt, vals_alt, run, npairs_out, splits, table, total;
+  uint32_t ntfo, ncount_tiles, nsort_tiles_cap, nmerge_tiles_cap;
+};
+
+Layout make_layout(uint64_t ntris, uint64_t cap_pairs, uint64_t ncells_plus_grids, const Plan& plan,
+                   uint32_t ngrids, bool batched) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + std::max<size_t>(bytes, 1));
+    return at;
+  };
+  L.ncount_tiles = static_cast<uint32_t>(ceil_div(ntris, kCountBlock * kCountK));
+  L.nsort_tiles_cap = static_cast<uint32_t>(ceil_div(cap_pairs, kSortTile));
+  L.ntfo = L.nsort_tiles_cap + 1;
+  L.nmerge_tiles_cap = static_cast<uint32_t>(ceil_div(ncells_plus_grids + cap_pairs, kMergeTile) + ngrids);
+  L.ctl = take(sizeof(Control));
+  L.hist = take(4 * kRadixMax * sizeof(uint32_t));
+  L.count_status = take(std::max<size_t>(L.ncount_tiles, 1) * 8);
+  L.zero_end = o;
+  L.start = take(ntris * 4);
+  L.box = take(ntris * 8);
+  L.tfo = take(static_cast<size_t>(L.ntfo) * 4);
+  L.sort_status = take(static_cast<size_t>(plan.sp.passes) * L.nsort_tiles_cap * (size_t{1} << plan.rb) * 8);
+  L.keys_alt = take(cap_pairs * 4);
+  L.vals_alt = take(cap_pairs * 4);
+  L.run = take((ngrids + 1) * sizeof(GridRun));
+  L.npairs_out = take(ngrids * 8);
+  L.splits = take(static_cast<size_t>(L.nmerge_tiles_cap) * 4);
+  L.table = take(batched ? ngrids * sizeof(GridDev) : 0);
+  L.total = o + 256;
+  return L;
+}
+
+template <class T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// ---- argument checks --------------------------------------------------------------
+bool finite(float x) { return std::isfinite(x); }
+
+int check_grid(const float lo[3], const float hi[3], const uint32_t res[3]) {
+  if (!lo || !hi || !res) return GRID_E_INVAL;
+  for (int a = 0; a < 3; ++a) {
+    if (!finite(lo[a]) || !finite(hi[a]) || !(lo[a] < hi[a])) return GRID_E_INVAL;
+    if (res[a] < 1 || res[a] > 1024) return GRID_E_INVAL;
+  }
+  return GRID_OK;
+}
+
+uint64_t ncells_of(const uint32_t res[3]) { return static_cast<uint64_t>(res[0]) * res[1] * res[2]; }
+
+GridDev make_grid(const float* verts, uint32_t nverts, const uint32_t* tris, uint32_t ntris, const float lo[3],
+                  const float hi[3], const uint32_t res[3]) {
+  GridDev g{};
+  g.verts = verts;
+  g.tris = tris;
+  g.nverts = nverts;
+  g.ntris = ntris;
+  for (int a = 0; a < 3; ++a) {
+    g.res[a] = res[a];
+    g.lo[a] = lo[a];
+    const float ext = hi[a] - lo[a];              // FP32, as the grid contract states
+    g.inv[a] = static_cast<float>(res[a]) / ext;  // IEEE division on the host
+  }
+  return g;
+}
+
+// ---- the launch sequence ------------------------------------------------------------
+__global__ void zero_kernel(uint64_t* p, uint64_t nwords) {
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < nwords;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    p[i] = 0;
+}
+
+int launch_zero(void* ws, size_t bytes, hipStream_t s) {
+  const uint64_t words = bytes / 8;
+  const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>(ceil_div(words, 256), 1024));
+  zero_kernel<<<std::max(blocks, 1u), 256, 0, s>>>(static_cast<uint64_t*>(ws), words);
+  GB_LAUNCHED();
+  return GRID_OK;
+}
+
+struct Build {
+  void* ws;
+  Layout L;
+  Plan plan;
+  GridSet gs;
+  uint32_t ntris;
+  bool batched;
+  hipStream_t s;
+};
+
+template <bool B>
+int launch_count(Build& b) {
+  if (b.ntris == 0) return GRID_OK;
+  CountArgs a{};
+  a.gs = b.gs;
+  a.ntris = b.ntris;
+  a.start = at<uint32_t>(b.ws, b.L.start);
+  a.box = at<uint64_t>(b.ws, b.L.box);
+  a.tfo = at<uint32_t>(b.ws, b.L.tfo);
+  a.ntfo = b.L.ntfo;
+  a.sort_tile_shift = kSortTileShift;
+  a.status = at<uint64_t>(b.ws, b.L.count_status);
+  a.ctl = at<Control>(b.ws, b.L.ctl);
+  count_kernel<kCountBlock, kCountK, B><<<b.L.ncount_tiles, kCountBlock, 0, b.s>>>(a);
+  GB_LAUNCHED();
+  return GRID_OK;
+}
+
+template <bool B>
+int launch_plan(Build& b) {
+  PlanArgs a{};
+  a.gs = b.gs;
+  a.start = at<uint32_t>(b.ws, b.L.start);
+  a.ntris = b.ntris;
+  a.merge_tile = kMergeTile;
+  a.run = at<GridRun>(b.ws, b.L.run);
+  a.npairs_out = at<uint64_t>(b.ws, b.L.npairs_out);
+  a.cap_flag = &at<Control>(b.ws, b.L.ctl)->pad0;
+  a.ctl = at<Control>(b.ws, b.L.ctl);
+  plan_kernel<kPlanBlock, B><<<1, kPlanBlock, 0, b.s>>>(a);
+  GB_LAUNCHED();
+  return GRID_OK;
+}
+
+ExpandArgs expand_args(const Build& b) {
+  ExpandArgs e{};
+  e.gs = b.gs;
+  e.start = at<uint32_t>(b.ws, b.L.start);
+  e.box = at<uint64_t>(b.ws, b.L.box);
+  e.tfo = at<uint32_t>(b.ws, b.L.tfo);
+  e.ntris = b.ntris;
+  return e;
+}
+
+uint32_t persistent_blocks(uint64_t tiles, int per_cu) {
+  const uint64_t cap = static_cast<uint64_t>(device_cus()) * per_cu;
+  return static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap)));
+}
+
+template <bool B>
+int launch_expand(Build& b, uint32_t* cells, uint32_t* objs, uint64_t npairs) {
+  if (npairs == 0) return GRID_OK;
+  ExpandOutArgs a{};
+  a.ex = expand_args(b);
+  a.cells = cells;
+  a.objs = objs;
+  a.ctl = at<Control>(b.ws, b.L.ctl);
+  expand_kernel<kSortBlock, kSortK, B><<<persistent_blocks(ceil_div(npairs, kSortTile), 4), kSortBlock, 0, b.s>>>(a);
+  GB_LAUNCHED();
+  return GRID_OK;
+}
+
+template <int RB, bool B>
+int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t npairs) {
+  const SortPlan& sp = b.plan.sp;
+  const uint32_t ntiles = static_cast<uint32_t>(ceil_div(npairs, kSortTile));
+  Control* ctl = at<Control>(b.ws, b.L.ctl);
+  {
+    HistArgs h{};
+    h.ex = expand_args(b);
+    h.plan = sp;
+    h.hist = at<uint32_t>(b.ws, b.L.hist);
+    h.sort_status = at<uint64_t>(b.ws, b.L.sort_status);
+    h.status_stride = static_cast<uint64_t>(b.L.nsort_tiles_cap) * (1u << RB);
+    h.ctl = ctl;
+    hist_kernel<kSortBlock, kSortK, RB, B><<<persistent_blocks(ntiles, 3), kSortBlock, 0, b.s>>>(h);
+    GB_LAUNCHED();
+  }
+  uint32_t* alt_k = at<uint32_t>(b.ws, b.L.keys_alt);
+  uint32_t* alt_v = at<uint32_t>(b.ws, b.L.vals_alt);
+  const uint32_t P = sp.passes;
+  const uint32_t blocks = persistent_blocks(ntiles, 2);
+  const uint32_t* in_k = nullptr;
+  const uint32_t* in_v = nullptr;
+  for (uint32_t p = 0; p < P; ++p) {
+    const bool to_out = ((P - 1 - p) % 2) == 0;
+    uint32_t* ok = to_out ? out_cells : alt_k;
+    uint32_t* ov = to_out ? out_objs : alt_v;
+    SortPassArgs a{};
+    a.keys_in = in_k;
+    a.vals_in = in_v;
+    a.keys_out = ok;
+    a.vals_out = ov;
+    a.ex = expand_args(b);
+    a.hist = at<uint32_t>(b.ws, b.L.hist) + p * kRadixMax;
+    a.status = at<uint64_t>(b.ws, b.L.sort_status) + static_cast<uint64_t>(p) * b.L.nsort_tiles_cap * (1u << RB);
+    a.n = npairs;
+    a.n_from_ctl = 1;
+    a.shift = sp.shift[p];
+    a.width = sp.width[p];
+    a.counter = kCtrSort0 + p;
+    a.run = at<GridRun>(b.ws, b.L.run);
+    a.ctl = ctl;
+    const bool last = p + 1 == P;
+    if (p == 0) {
+      if (B && last)
+        onesweep_kernel<kSortBlock, kSortK, RB, kFromExpansion, kToGrids, B><<<blocks, kSortBlock, 0, b.s>>>(a);
+      else
+        onesweep_kernel<kSortBlock, kSortK, RB, kFromExpansion, kToArrays, B><<<blocks, kSortBlock, 0, b.s>>>(a);
+    } else {
+      if (B && last)
+        onesweep_kernel<kSortBlock, kSortK, RB, kFromArrays, kToGrids, B><<<blocks, kSortBlock, 0, b.s>>>(a);
+      else
+        onesweep_kernel<kSortBlock, kSortK, RB, kFromArrays, kToArrays, B><<<blocks, kSortBlock, 0, b.s>>>(a);
+    }
+    GB_LAUNCHED();
+    in_k = ok;
+    in_v = ov;
+  }
+  return GRID_OK;
+}
+
+template <bool B>
+int launch_sort(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t npairs) {
+  switch (b.plan.rb) {
+    case 8: return launch_sort_rb<8, B>(b, out_cells, out_objs, npairs);
+    case 9: return launch_sort_rb<9, B>(b, out_cells, out_objs, npairs);
+    case 10: return launch_sort_rb<10, B>(b, out_cells, out_objs, npairs);
+    case 11: return launch_sort_rb<11, B>(b, out_cells, out_objs, npairs);
+    default: return GRID_E_INVAL;
+  }
+}
+
+template <bool B>
+int launch_ranges(Build& b, uint64_t merge_items_cap) {
+  RangesArgs a{};
+  a.gs = b.gs;
+  a.run = at<GridRun>(b.ws, b.L.run);
+  a.splits = at<uint32_t>(b.ws, b.L.splits);
+  a.merge_tile = kMergeTile;
+  a.ctl = at<Control>(b.ws, b.L.ctl);
+  const uint64_t tiles = ceil_div(merge_items_cap, kMergeTile) + b.gs.ngrids;
+  split_kernel<256, B><<<static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(tiles, 256), 4096))),
+                         256, 0, b.s>>>(a);
+  GB_LAUNCHED();
+  ranges_kernel<kRangesBlock, kRangesK, B><<<persistent_blocks(tiles, 8), kRangesBlock, 0, b.s>>>(a);
+  GB_LAUNCHED();
+  return GRID_OK;
+}
+
+struct HostCtl {
+  uint64_t npairs;
+  uint32_t error;
+  uint32_t cap_flag;
+};
+
+int read_ctl(const Build& b, HostCtl* h) {
+  Control c;
+  GB_TRY(hipMemcpyAsync(&c, at<Control>(b.ws, b.L.ctl), sizeof(Control), hipMemcpyDeviceToHost, b.s));
+  GB_TRY(hipStreamSynchronize(b.s));
+  h->npairs = c.npairs;
+  h->error = c.error;
+  h->cap_flag = c.pad0;
+  return GRID_OK;
+}
+
+int prepare_plain(Build& b, const float* verts, uint32_t nverts, const uint32_t* tris, uint32_t ntris,
+                  const float lo[3], const float hi[3], const uint32_t res[3], void* ws, size_t ws_bytes,
+                  uint64_t cap_pairs, hipStream_t s) {
+  int st = check_grid(lo, hi, res);
+  if (st != GRID_OK) return st;
+  if (!ws) return GRID_E_INVAL;
+  if (ntris > 0 && (!verts || !tris)) return GRID_E_INVAL;
+  if (ntris >= (1u << 31)) return GRID_E_INVAL;
+  b.ws = ws;
+  b.s = s;
+  b.ntris = ntris;
+  b.batched = false;
+  b.plan = make_plan(bits_for(ncells_of(res)));
+  b.L = make_layout(ntris, cap_pairs, ncells_of(res) + 1, b.plan, 1, false);
+  if (ws_bytes < b.L.total) return GRID_E_NOMEM;
+  b.gs = GridSet{};
+  b.gs.one = make_grid(verts, nverts, tris, ntris, lo, hi, res);
+  b.gs.one.cap_pairs = cap_pairs;
+  b.gs.ngrids = 1;
+  return GRID_OK;
+}
+
+int count_phase_plain(Build& b, HostCtl* h) {
+  int st = launch_zero(b.ws, b.L.zero_end, b.s);
+  if (st) return st;
+  if ((st = launch_count<false>(b))) return st;
+  if ((st = read_ctl(b, h))) return st;
+  if (h->error & kErrBadIndex) return GRID_E_BADINDEX;
+  if (h->npairs > 0xFFFFFFFFull) return GRID_E_OVERFLOW;
+  return GRID_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* grid_strerror(int status) {
+  switch (status) {
+    case GRID_OK: return "ok";
+    case GRID_E_INVAL: return "invalid argument";
+    case GRID_E_NOMEM: return "workspace too small";
+    case GRID_E_OVERFLOW: return "pair count exceeds 2^32 - 1";
+    case GRID_E_CAPACITY: return "pair capacity too small";
+    case GRID_E_BADINDEX: return "vertex index out of range";
+    case GRID_E_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+size_t grid_workspace_size(uint32_t ntris, uint64_t cap_pairs, const uint32_t res[3]) {
+  if (!res) return 0;
+  const uint64_t nc = ncells_of(res);
+  return make_layout(ntris, cap_pairs, nc + 1, make_plan(bits_for(nc)), 1, false).total;
+}
+
+int grid_count(const float* verts_soa, uint32_t nverts, const uint32_t* tris, uint32_t ntris, const float lo[3],
+               const float hi[3], const uint32_t res[3], void* ws, size_t ws_bytes, uint32_t* start_out,
+               uint64_t* npairs, void* stream) {
+  if (!npairs) return GRID_E_INVAL;
+  Build b{};
+  // the count needs no pair buffers: size the layout for zero pairs
+  int st = prepare_plain(b, verts_soa, nverts, tris, ntris, lo, hi, res, ws, ws_bytes, 0,
+                         static_cast<hipStream_t>(stream));
+  if (st) return st;
+  HostCtl h{};
+  st = count_phase_plain(b, &h);
+  *npairs = h.npairs;
+  if (st == GRID_OK && start_out && ntris > 0) {
+    GB_TRY(hipMemcpyAsync(start_out, at<uint32_t>(ws, b.L.start), static_cast<size_t>(ntris) * 4,
+                          hipMemcpyDeviceToDevice, b.s));
+    GB_TRY(hipStreamSynchronize(b.s));
+  }
+  return st;
+}
+
+int grid_build(const float* verts_soa, uint32_t nverts, const uint32_t* tris, uint32_t ntris, const float lo[3],
+               const float hi[3], const uint32_t res[3], void* ws, size_t ws_bytes, grid_out* out, void* stream) {
+  if (!out || !out->ranges || (out->cap_pairs > 0 && (!out->cells || !out->objs))) return GRID_E_INVAL;
+  Build b{};
+  int st = prepare_plain(b, verts_soa, nverts, tris, ntris, lo, hi, res, ws, ws_bytes, out->cap_pairs,
+                         static_cast<hipStream_t>(stream));
+  if (st) return st;
+  b.gs.one.out_cells = out->cells;
+  b.gs.one.out_objs = out->objs;
+  b.gs.one.out_ranges = out->ranges;
+  HostCtl h{};
+  st = count_phase_plain(b, &h);
+  out->npairs = h.npairs;
+  if (st) return st;
+  if (h.npairs > out->cap_pairs) return GRID_E_CAPACITY;
+  if ((st = launch_plan<false>(b))) return st;
+  if (b.plan.sp.passes == 0) {
+    if ((st = launch_expand<false>(b, out->cells, out->objs, h.npairs))) return st;
+  } else if (h.npairs > 0) {
+    if ((st = launch_sort<false>(b, out->cells, out->objs, h.npairs))) return st;
+  }
+  return launch_ranges<false>(b, ncells_of(res) + 1 + h.npairs);
+}
+
+int grid_expand(const float* verts_soa, uint32_t nverts, const uint32_t* tris, uint32_t ntris, const float lo[3],
+                const float hi[3], const uint32_t res[3], void* ws, size_t ws_bytes, uint32_t* cells, uint32_t* objs,
+                uint64_t cap_pairs, uint64_t* npairs, void* stream) {
+  if (!npairs || (cap_pairs > 0 && (!cells || !objs))) return GRID_E_INVAL;
+  Build b{};
+  int st = prepare_plain(b, verts_soa, nverts, tris, ntris, lo, hi, res, ws, ws_bytes, cap_pairs,
+                         static_cast<hipStream_t>(stream));
+  if (st) return st;
+  HostCtl h{};
+  st = count_phase_plain(b, &h);
+  *npairs = h.npairs;
+  if (st) return st;
+  if (h.npairs > cap_pairs) return GRID_E_CAPACITY;
+  if ((st = launch_expand<false>(b, cells, objs, h.npairs))) return st;
+  GB_TRY(hipStreamSynchronize(b.s));
+  return GRID_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// Batched builds.
+// ---------------------------------------------------------------------------------
+namespace {
+
+struct BatchSetup {
+  std::vector<GridDev> table;
+  uint64_t ntris = 0, cap = 0, cells = 0;
+  uint32_t cell_bits = 0, grid_bits = 0;
+};
+
+int setup_batch(const grid_desc* grids, uint32_t ngrids, BatchSetup* bs, bool need_out) {
+  if (!grids || ngrids == 0) return GRID_E_INVAL;
+  bs->table.resize(ngrids);
+  for (uint32_t g = 0; g < ngrids; ++g) {
+    const grid_desc& d = grids[g];
+    int st = check_grid(d.lo, d.hi, d.res);
+    if (st) return st;
+    if (d.ntris > 0 && (!d.verts_soa || !d.tris)) return GRID_E_INVAL;
+    if (need_out && (!d.out.ranges || (d.out.cap_pairs > 0 && (!d.out.cells || !d.out.objs)))) return GRID_E_INVAL;
+    GridDev gd = make_grid(d.verts_soa, d.nverts, d.tris, d.ntris, d.lo, d.hi, d.res);
+    gd.out_cells = d.out.cells;
+    gd.out_objs = d.out.objs;
+    gd.out_ranges = d.out.ranges;
+    gd.cap_pairs = need_out ? d.out.cap_pairs : ~uint64_t{0};
+    gd.tri_base = static_cast<uint32_t>(bs->ntris);
+    gd.cell_base = bs->cells;
+    bs->table[g] = gd;
+    bs->ntris += d.ntris;
+    bs->cap += need_out ? d.out.cap_pairs : 0;
+    bs->cells += ncells_of(d.res);
+    bs->cell_bits = std::max(bs->cell_bits, bits_for(ncells_of(d.res)));
+  }
+  if (bs->ntris >= (1u << 31)) return GRID_E_INVAL;
+  bs->grid_bits = bits_for(ngrids);
+  return GRID_OK;
+}
+
+// Largest run of grids starting at g0 whose packed keys fit in 32 bits.
+uint32_t batch_chunk(const grid_desc* grids, uint32_t ngrids, uint32_t g0) {
+  uint32_t cb = 0, n = 0;
+  while (g0 + n < ngrids) {
+    const uint32_t cb2 = std::max(cb, bits_for(ncells_of(grids[g0 + n].res)));
+    if (cb2 + bits_for(n + 1) > 32) break;
+    cb = cb2;
+    ++n;
+  }
+  return std::max(n, 1u);
+}
+
+int prepare_batched(Build& b, BatchSetup& bs, const grid_desc* grids, uint32_t ngrids, void* ws, size_t ws_bytes,
+                    hipStream_t s, bool need_out) {
+  int st = setup_batch(grids, ngrids, &bs, need_out);
+  if (st) return st;
+  if (bs.cell_bits + bs.grid_bits > 32) return GRID_E_INVAL;
+  b.ws = ws;
+  b.s = s;
+  b.ntris = static_cast<uint32_t>(bs.ntris);
+  b.batched = true;
+  b.plan = make_plan(std::max(1u, bs.cell_bits + bs.grid_bits));
+  b.L = make_layout(bs.ntris, bs.cap, bs.cells + ngrids, b.plan, ngrids, true);
+  if (!ws) return GRID_E_INVAL;
+  if (ws_bytes < b.L.total) return GRID_E_NOMEM;
+  b.gs = GridSet{};
+  b.gs.table = at<GridDev>(ws, b.L.table);
+  b.gs.ngrids = ngrids;
+  b.gs.cell_bits = bs.cell_bits;
+  GB_TRY(hipMemcpyAsync(at<GridDev>(ws, b.L.table), bs.table.data(), ngrids * sizeof(GridDev),
+                        hipMemcpyHostToDevice, s));
+  return GRID_OK;
+}
+
+int count_phase_batched(Build& b, uint32_t ngrids, std::vector<uint64_t>& npairs, HostCtl* h) {
+  int st = launch_zero(b.ws, b.L.zero_end, b.s);
+  if (st) return st;
+  if ((st = launch_count<true>(b))) return st;
+  if ((st = launch_plan<true>(b))) return st;
+  npairs.resize(ngrids);
+  GB_TRY(hipMemcpyAsync(npairs.data(), at<uint64_t>(b.ws, b.L.npairs_out), ngrids * 8, hipMemcpyDeviceToHost, b.s));
+  if ((st = read_ctl(b, h))) return st;
+  if (h->error & kErrBadIndex) return GRID_E_BADINDEX;
+  if (h->npairs > 0xFFFFFFFFull) return GRID_E_OVERFLOW;
+  return GRID_OK;
+}
+
+size_t batched_ws_one(const grid_desc* grids, uint32_t ngrids, bool need_out) {
+  BatchSetup bs;
+  if (setup_batch(grids, ngrids, &bs, need_out)) return 0;
+  return make_layout(bs.ntris, bs.cap, bs.cells + ngrids, make_plan(std::max(1u, bs.cell_bits + bs.grid_bits)), ngrids,
+                     true).total;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t grid_workspace_size_batched(const grid_desc* grids, uint32_t ngrids) {
+  size_t need = 0;
+  for (uint32_t g0 = 0; g0 < ngrids;) {
+    const uint32_t n = batch_chunk(grids, ngrids, g0);
+    need = std::max(need, batched_ws_one(grids + g0, n, true));
+    g0 += n;
+  }
+  return need;
+}
+
+int grid_count_batched(grid_desc* grids, uint32_t ngrids, void* ws, size_t ws_bytes, void* stream) {
+  if (!grids || ngrids == 0) return GRID_E_INVAL;
+  for (uint32_t g0 = 0; g0 < ngrids;) {
+    const uint32_t n = batch_chunk(grids, ngrids, g0);
+    Build b{};
+    BatchSetup bs;
+    int st = prepare_batched(b, bs, grids + g0, n, ws, ws_bytes, static_cast<hipStream_t>(stream), false);
+    if (st) return st;
+    std::vector<uint64_t> np;
+    HostCtl h{};
+    st = count_phase_batched(b, n, np, &h);
+    if (st) return st;
+    for (uint32_t g = 0; g < n; ++g) grids[g0 + g].out.npairs = np[g];
+    g0 += n;
+  }
+  return GRID_OK;
+}
+
+int grid_build_batched(grid_desc* grids, uint32_t ngrids, void* ws, size_t ws_bytes, void* stream) {
+  if (!grids || ngrids == 0) return GRID_E_INVAL;
+  for (uint32_t g0 = 0; g0 < ngrids;) {
+    const uint32_t n = batch_chunk(grids, ngrids, g0);
+    Build b{};
+    BatchSetup bs;
+    int st = prepare_batched(b, bs, grids + g0, n, ws, ws_bytes, static_cast<hipStream_t>(stream), true);
+    if (st) return st;
+    std::vector<uint64_t> np;
+    HostCtl h{};
+    st = count_phase_batched(b, n, np, &h);
+    if (st) return st;
+    bool cap_ok = true;
+    for (uint32_t g = 0; g < n; ++g) {
+      grids[g0 + g].out.npairs = np[g];
+      if (np[g] > grids[g0 + g].out.cap_pairs) cap_ok = false;
+    }
+    if (!cap_ok) return GRID_E_CAPACITY;
+    if (h.npairs > 0) {
+      if (b.plan.sp.passes == 0) return GRID_E_INVAL;  // cannot happen: the grid bits alone need a pass
+      if ((st = launch_sort<true>(b, nullptr, nullptr, h.npairs))) return st;
+    }
+    if ((st = launch_ranges<true>(b, bs.cells + n + h.npairs))) return st;
+    g0 += n;
+  }
+  return GRID_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// Building blocks: the radix sort and the scans on their own.
+// ---------------------------------------------------------------------------------
+namespace {
+
+struct SortLayout {
+  size_t ctl, hist, status, total;
+  uint32_t ntiles;
+};
+
+SortLayout sort_layout(uint64_t n, const Plan& plan) {
+  SortLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + std::max<size_t>(bytes, 1));
+    return at;
+  };
+  L.ntiles = static_cast<uint32_t>(ceil_div(n, kSortTile));
+  L.ctl = take(sizeof(Control));
+  L.hist = take(4 * kRadixMax * sizeof(uint32_t));
+  L.status = take(static_cast<size_t>(plan.sp.passes) * L.ntiles * (size_t{1} << plan.rb) * 8);
+  L.total = o + 256;
+  return L;
+}
+
+template <int RB>
+int sort_arrays_rb(uint32_t* keys, uint32_t* vals, uint32_t* ka, uint32_t* va, uint64_t n, const Plan& plan,
+                   void* ws, const SortLayout& L, hipStream_t s) {
+  Control* ctl = at<Control>(ws, L.ctl);
+  const uint64_t stride = static_cast<uint64_t>(L.ntiles) * (1u << RB);
+  {
+    HistArrayArgs h{};
+    h.keys = keys;
+    h.n = n;
+    h.plan = plan.sp;
+    h.hist = at<uint32_t>(ws, L.hist);
+    h.sort_status = at<uint64_t>(ws, L.status);
+    h.status_stride = stride;
+    h.ctl = ctl;
+    hist_array_kernel<kSortBlock, kSortK, RB><<<persistent_blocks(L.ntiles, 3), kSortBlock, 0, s>>>(h);
+    GB_LAUNCHED();
+  }
+  uint32_t* src_k = keys;
+  uint32_t* src_v = vals;
+  uint32_t* dst_k = ka;
+  uint32_t* dst_v = va;
+  for (uint32_t p = 0; p < plan.sp.passes; ++p) {
+    SortPassArgs a{};
+    a.keys_in = src_k;
+    a.vals_in = src_v;
+    a.keys_out = dst_k;
+    a.vals_out = dst_v;
+    a.hist = at<uint32_t>(ws, L.hist) + p * kRadixMax;
+    a.status = at<uint64_t>(ws, L.status) + p * stride;
+    a.n = n;
+    a.n_from_ctl = 0;
+    a.shift = plan.sp.shift[p];
+    a.width = plan.sp.width[p];
+    a.counter = kCtrSort0 + p;
+    a.ctl = ctl;
+    onesweep_kernel<kSortBlock, kSortK, RB, kFromArrays, kToArrays, false>
+        <<<persistent_blocks(L.ntiles, 2), kSortBlock, 0, s>>>(a);
+    GB_LAUNCHED();
+    std::swap(src_k, dst_k);
+    std::swap(src_v, dst_v);
+  }
+  if (src_k != keys) {
+    GB_TRY(hipMemcpyAsync(keys, src_k, n * 4, hipMemcpyDeviceToDevice, s));
+    GB_TRY(hipMemcpyAsync(vals, src_v, n * 4, hipMemcpyDeviceToDevice, s));
+  }
+  return GRID_OK;
+}
+
+size_t scan_layout_status(uint64_t n) { return align_up(sizeof(Control)); }
+uint32_t scan_tiles(uint64_t n) { return static_cast<uint32_t>(ceil_div(n, kScanBlock * kScanK)); }
+
+}  // namespace
+
+extern "C" {
+
+size_t grid_sort_workspace_size(uint64_t n, uint32_t nbits) {
+  if (nbits > 32) return 0;
+  return sort_layout(n, make_plan(nbits)).total;
+}
+
+int grid_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, uint64_t n,
+                    uint32_t nbits, void* ws, size_t ws_bytes, void* stream) {
+  if (nbits > 32 || n > 0xFFFFFFFFull) return GRID_E_INVAL;
+  if (n == 0 || nbits == 0) return GRID_OK;
+  if (!keys || !vals || !keys_alt || !vals_alt || !ws) return GRID_E_INVAL;
+  const Plan plan = make_plan(nbits);
+  const SortLayout L = sort_layout(n, plan);
+  if (ws_bytes < L.total) return GRID_E_NOMEM;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int st = launch_zero(ws, L.status, s);  // control block and histograms
+  if (st) return st;
+  switch (plan.rb) {
+    case 8: return sort_arrays_rb<8>(keys, vals, keys_alt, vals_alt, n, plan, ws, L, s);
+    case 9: return sort_arrays_rb<9>(keys, vals, keys_alt, vals_alt, n, plan, ws, L, s);
+    case 10: return sort_arrays_rb<10>(keys, vals, keys_alt, vals_alt, n, plan, ws, L, s);
+    case 11: return sort_arrays_rb<11>(keys, vals, keys_alt, vals_alt, n, plan, ws, L, s);
+    default: return GRID_E_INVAL;
+  }
+}
+
+size_t grid_scan_workspace_size(uint64_t n) {
+  return scan_layout_status(n) + align_up(std::max<uint64_t>(scan_tiles(n), 1) * 8) + 256;
+}
+
+int grid_scan_u32(const uint32_t* in, const uint32_t* flags, uint32_t* out, uint64_t n, int op, void* ws,
+                  size_t ws_bytes, uint64_t* total, void* stream) {
+  if (!total || op < 0 || op > 2) return GRID_E_INVAL;
+  *total = 0;
+  if (n == 0) return GRID_OK;
+  if (!in || !out || !ws || (op == GRID_SCAN_SEGMENTED_EXCLUSIVE_SUM && !flags)) return GRID_E_INVAL;
+  if (ws_bytes < grid_scan_workspace_size(n)) return GRID_E_NOMEM;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t status_off = scan_layout_status(n);
+  const uint32_t tiles = scan_tiles(n);
+  int st = launch_zero(ws, status_off + static_cast<size_t>(tiles) * 8, s);
+  if (st) return st;
+  ScanArgs a{};
+  a.in = in;
+  a.flags = flags;
+  a.out = out;
+  a.n = n;
+  a.status = at<uint64_t>(ws, status_off);
+  a.ctl = at<Control>(ws, 0);
+  if (op == GRID_SCAN_EXCLUSIVE_SUM)
+    scan_kernel<kScanBlock, kScanK, ScanSum, 0><<<tiles, kScanBlock, 0, s>>>(a);
+  else if (op == GRID_SCAN_INCLUSIVE_MAX)
+    scan_kernel<kScanBlock, kScanK, ScanMax, 1><<<tiles, kScanBlock, 0, s>>>(a);
+  else
+    scan_kernel<kScanBlock, kScanK, ScanSeg, 2><<<tiles, kScanBlock, 0, s>>>(a);
+  GB_LAUNCHED();
+  Control c;
+  GB_TRY(hipMemcpyAsync(&c, ws, sizeof(Control), hipMemcpyDeviceToHost, s));
+  GB_TRY(hipStreamSynchronize(s));
+  uint64_t t = c.scratch[0];
+  if (op == GRID_SCAN_SEGMENTED_EXCLUSIVE_SUM) t &= ScanSeg::kSum;
+  *total = t;
+  return GRID_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,348 @@
+// The kernels of one build: count+scan, expansion, radix-sort passes and
+// per-cell ranges.  Every kernel that runs after the count reads the pair count
+// from device memory, so a whole build is a fixed sequence of launches.
+#pragma once
+
+#include "common.hpp"
+#include "grid.hpp"
+
+namespace gb {
+
+enum CounterSlot : uint32_t {
+  kCtrCount = 0, kCtrHist = 1, kCtrExpand = 2, kCtrSort0 = 3,  // sort passes use 3..6
+  kCtrSplit = 8, kCtrRanges = 9, kCtrScan = 10, kCtrPlan = 11,
+};
+
+// ---------------------------------------------------------------------------
+// Grid lookup.  Plain builds carry their one grid in the kernel arguments;
+// batched builds read a device table and find the grid of a triangle from the
+// grids' first-triangle indices.
+// ---------------------------------------------------------------------------
+struct GridSet {
+  GridDev one;              // plain builds
+  const GridDev* table;     // batched builds (device)
+  uint32_t ngrids;
+  uint32_t cell_bits;       // batched: key = (grid << cell_bits) | cell
+};
+
+template <bool Batched>
+GB_DEV const GridDev& grid_at(const GridSet& s, uint32_t g) {
+  if constexpr (Batched) return s.table[g]; else return s.one;
+}
+
+// Smallest g with tri_base[g + 1] > t, starting from a lower bound g.
+template <bool Batched>
+GB_DEV uint32_t grid_of_tri(const GridSet& s, uint32_t t, uint32_t g) {
+  if constexpr (Batched) {
+    while (g + 1 < s.ngrids && s.table[g + 1].tri_base <= t) ++g;
+    return g;
+  } else {
+    return 0;
+  }
+}
+
+// First grid whose triangle range contains t (binary search over the table).
+template <bool Batched>
+GB_DEV uint32_t grid_search(const GridSet& s, uint32_t t) {
+  if constexpr (Batched) {
+    uint32_t lo = 0, hi = s.ngrids;  // answer in [lo, hi)
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (s.table[mid].tri_base <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+  } else {
+    return 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CountCells + ExclusiveSum (one pass, decoupled look-back).
+// ---------------------------------------------------------------------------
+struct CountArgs {
+  GridSet gs;
+  uint32_t ntris;           // total triangles (all grids)
+  uint32_t* start;          // [ntris] exclusive pair offsets (global)
+  uint64_t* box;            // [ntris] packed cell boxes
+  uint32_t* tfo;            // [ntfo] owner of the first pair of each sort tile
+  uint32_t ntfo;
+  uint32_t sort_tile_shift; // log2 of the sort tile size
+  uint64_t* status;         // [count tiles] look-back words
+  Control* ctl;
+};
+
+template <int Block, int K, bool Batched>
+__global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
+  constexpr int Tile = Block * K;
+  __shared__ uint32_t s_val[Tile];
+  __shared__ uint64_t s_wtot[Block / kWave];
+  __shared__ uint64_t s_prefix;
+  __shared__ uint32_t s_tile;
+  const uint32_t tile = next_tile(&a.ctl->tile_counter[kCtrCount], &s_tile);
+  const uint32_t tid = threadIdx.x;
+  const uint64_t base = static_cast<uint64_t>(tile) * Tile;
+  const uint32_t ntiles = (a.ntris + Tile - 1) / Tile;
+  uint32_t g = Batched && base < a.ntris ? grid_search<Batched>(a.gs, static_cast<uint32_t>(base)) : 0;
+
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint64_t t = base + static_cast<uint64_t>(k) * Block + tid;
+    uint32_t cnt = 0;
+    if (t < a.ntris) {
+      g = grid_of_tri<Batched>(a.gs, static_cast<uint32_t>(t), g);
+      const GridDev& G = grid_at<Batched>(a.gs, g);
+      const uint32_t lt = static_cast<uint32_t>(t) - G.tri_base;
+      const uint32_t* tri = G.tris + 3 * static_cast<uint64_t>(lt);
+      const uint32_t i0 = tri[0], i1 = tri[1], i2 = tri[2];
+      uint64_t packed = 0;
+      cnt = 1;
+      if (i0 >= G.nverts || i1 >= G.nverts || i2 >= G.nverts) {
+        atomicOr(&a.ctl->error, kErrBadIndex);
+      } else {
+        uint32_t lo[3], m[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const float* v = G.verts + static_cast<uint64_t>(ax) * G.nverts;
+          const float p0 = v[i0], p1 = v[i1], p2 = v[i2];
+          const float pmin = fminf(fminf(p0, p1), p2);
+          const float pmax = fmaxf(fmaxf(p0, p1), p2);
+          const uint32_t cl = cell_coord(pmin, G.lo[ax], G.inv[ax], G.res[ax] - 1);
+          const uint32_t ch = cell_coord(pmax, G.lo[ax], G.inv[ax], G.res[ax] - 1);
+          lo[ax] = cl;
+          m[ax] = ch - cl + 1;
+        }
+        cnt = m[0] * m[1] * m[2];
+        packed = pack_box(lo, m);
+      }
+      a.box[t] = packed;
+    }
+    s_val[k * Block + tid] = cnt;
+  }
+  __syncthreads();
+
+  uint32_t mine[K];
+  uint64_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    mine[k] = s_val[tid * K + k];
+    sum += mine[k];
+  }
+  uint64_t total;
+  uint64_t excl = block_exclusive_sum64<Block>(sum, s_wtot, total);
+  if (tid < kWave) {
+    const uint64_t p = lookback_wave(a.status, tile, total);
+    if (tid == 0) {
+      s_prefix = p;
+      if (tile == ntiles - 1) a.ctl->npairs = p + total;
+    }
+  }
+  __syncthreads();
+  excl += s_prefix;
+
+  const uint64_t tmask = (uint64_t{1} << a.sort_tile_shift) - 1;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint64_t t = base + static_cast<uint64_t>(tid) * K + k;
+    s_val[tid * K + k] = static_cast<uint32_t>(excl);
+    if (mine[k] != 0 && t < a.ntris) {
+      // sort tiles whose first pair this object owns
+      uint64_t j = (excl + tmask) >> a.sort_tile_shift;
+      const uint64_t jlast = (excl + mine[k] - 1) >> a.sort_tile_shift;
+      for (; j <= jlast && j < a.ntfo; ++j) a.tfo[j] = static_cast<uint32_t>(t);
+    }
+    excl += mine[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint64_t t = base + static_cast<uint64_t>(k) * Block + tid;
+    if (t < a.ntris) a.start[t] = s_val[k * Block + tid];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Expansion of one sort tile: pairs [tile * N, tile * N + n) -> (key, value),
+// in the wave-striped layout (item k of lane l in wave w is pair
+// tile * N + w * 64 * K + k * 64 + l).
+//
+// The owner of each pair is found as in the paper's MakeObjectIds +
+// InclusiveSum, in its max form: every object writes its id at its first pair
+// slot and an inclusive max-scan spreads it over its slots (the tile's first
+// slot is seeded with the owner of the tile's first pair).  The relative cell
+// offset is the pair index minus the owner's start (the segmented exclusive
+// sum of ones), and GlobalCoords maps it into the owner's box.
+// ---------------------------------------------------------------------------
+struct ExpandArgs {
+  GridSet gs;
+  const uint32_t* start;    // [ntris] global pair offsets
+  const uint64_t* box;      // [ntris]
+  const uint32_t* tfo;      // [ntiles + ...] owner of each tile's first pair
+  uint32_t ntris;           // total triangles
+};
+
+template <int Block, int K, bool Batched>
+GB_DEV void expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs, uint32_t ntiles, uint32_t* s_owner,
+                        uint32_t* s_wtot, uint32_t (&keys)[K], uint32_t (&vals)[K]) {
+  constexpr int N = Block * K;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t base = static_cast<uint64_t>(tile) * N;
+  const uint32_t n = static_cast<uint32_t>(npairs - base < N ? npairs - base : N);
+  const uint32_t t0 = a.tfo[tile];
+  const uint32_t thi = tile + 1 < ntiles ? a.tfo[tile + 1] : a.ntris - 1;
+#pragma unroll
+  for (int k = 0; k < K; ++k) s_owner[k * Block + tid] = 0;
+  __syncthreads();
+  if (tid == 0) s_owner[0] = t0;
+  for (uint32_t t = t0 + 1 + tid; t <= thi; t += Block) {
+    const uint64_t s = a.start[t];
+    if (s < base + n) s_owner[s - base] = t;
+  }
+  __syncthreads();
+  // inclusive max-scan over the tile's slots, K consecutive slots per thread
+  uint32_t run = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t v = s_owner[tid * K + k];
+    run = run > v ? run : v;
+  }
+  const uint32_t before = block_exclusive_max<Block>(run, s_wtot);
+  run = before;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t v = s_owner[tid * K + k];
+    run = run > v ? run : v;
+    s_owner[tid * K + k] = run;
+  }
+  __syncthreads();
+  const uint32_t lane = lane_id();
+  const uint32_t w = tid / kWave;
+  uint32_t gcur = 0;
+  if constexpr (Batched) gcur = grid_search<true>(a.gs, t0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t idx = w * (kWave * K) + k * kWave + lane;
+    if (idx < n) {
+      const uint32_t t = s_owner[idx];
+      const uint32_t rid = static_cast<uint32_t>(base + idx) - a.start[t];
+      const Box b = unpack_box(a.box[t]);
+      uint32_t g = grid_of_tri<Batched>(a.gs, t, gcur);
+      const GridDev& G = grid_at<Batched>(a.gs, g);
+      const uint32_t cell = cell_of(b, rid, G.res[0], G.res[0] * G.res[1]);
+      if constexpr (Batched) {
+        keys[k] = (g << a.gs.cell_bits) | cell;
+        vals[k] = t - G.tri_base;
+      } else {
+        keys[k] = cell;
+        vals[k] = t;
+      }
+    } else {
+      keys[k] = 0xFFFFFFFFu;
+      vals[k] = 0;
+    }
+  }
+  __syncthreads();
+}
+
+// Object-order pair lists written out (the expansion on its own).
+struct ExpandOutArgs {
+  ExpandArgs ex;
+  uint32_t* cells;
+  uint32_t* objs;
+  uint32_t tile_shift;
+  Control* ctl;
+};
+
+template <int Block, int K, bool Batched>
+__global__ __launch_bounds__(Block) void expand_kernel(ExpandOutArgs a) {
+  constexpr int N = Block * K;
+  __shared__ uint32_t s_owner[N];
+  __shared__ uint32_t s_wtot[Block / kWave];
+  __shared__ uint32_t s_tile;
+  const uint64_t npairs = a.ctl->npairs;
+  const uint32_t ntiles = static_cast<uint32_t>((npairs + N - 1) / N);
+  while (true) {
+    const uint32_t tile = next_tile(&a.ctl->tile_counter[kCtrExpand], &s_tile);
+    if (tile >= ntiles) break;
+    uint32_t keys[K], vals[K];
+    expand_tile<Block, K, Batched>(a.ex, tile, npairs, ntiles, s_owner, s_wtot, keys, vals);
+    const uint64_t base = static_cast<uint64_t>(tile) * N;
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint64_t i = base + w * (kWave * K) + k * kWave + lane;
+      if (i < npairs) {
+        a.cells[i] = keys[k];
+        a.objs[i] = vals[k];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Radix sort plan: up to 4 passes over the low `bits` bits of the key.
+// ---------------------------------------------------------------------------
+struct SortPlan {
+  uint32_t passes;
+  uint32_t shift[4];
+  uint32_t width[4];
+};
+
+// One read of the keys (regenerated from the expansion) for the digit
+// histograms of every pass; also clears the look-back words of every pass.
+struct HistArgs {
+  ExpandArgs ex;
+  SortPlan plan;
+  uint32_t* hist;           // [4][kRadixMax]
+  uint64_t* sort_status;    // [passes][status_stride]
+  uint64_t status_stride;   // words per pass (capacity tiles * radix)
+  Control* ctl;
+};
+
+constexpr int kRadixMax = 2048;
+
+template <int Block, int K, int RB, bool Batched>
+__global__ __launch_bounds__(Block) void hist_kernel(HistArgs a) {
+  constexpr int N = Block * K;
+  constexpr int R = 1 << RB;
+  __shared__ uint32_t s_owner[N];
+  __shared__ uint32_t s_hist[4 * R];
+  __shared__ uint32_t s_wtot[Block / kWave];
+  __shared__ uint32_t s_tile;
+  const uint64_t npairs = a.ctl->npairs;
+  const uint32_t ntiles = static_cast<uint32_t>((npairs + N - 1) / N);
+  // clear the sort passes' look-back words
+  {
+    const uint64_t per_pass = static_cast<uint64_t>(ntiles) * R;
+    const uint64_t nwords = static_cast<uint64_t>(a.plan.passes) * per_pass;
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * Block + threadIdx.x; i < nwords;
+         i += static_cast<uint64_t>(gridDim.x) * Block)
+      a.sort_status[(i / per_pass) * a.status_stride + i % per_pass] = 0;
+  }
+  for (int i = threadIdx.x; i < 4 * R; i += Block) s_hist[i] = 0;
+  __syncthreads();
+  while (true) {
+    const uint32_t tile = next_tile(&a.ctl->tile_counter[kCtrHist], &s_tile);
+    if (tile >= ntiles) break;
+    uint32_t keys[K], vals[K];
+    expand_tile<Block, K, Batched>(a.ex, tile, npairs, ntiles, s_owner, s_wtot, keys, vals);
+    const uint64_t base = static_cast<uint64_t>(tile) * N;
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint64_t i = base + w * (kWave * K) + k * kWave + lane;
+      if (i < npairs) {
+        for (uint32_t p = 0; p < a.plan.passes; ++p) {
+          const uint32_t d = (keys[k] >> a.plan.shift[p]) & ((1u << a.plan.width[p]) - 1u);
+          atomicAdd(&s_hist[p * R + d], 1u);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < a.plan.passes * R; i += Block) {
+    const uint32_t v = s_hist[i];
+    if (v) atomicAdd(&a.hist[(i / R) * kRadixMax + (i % R)], v);
+  }
+}
+
+}  // namespace gb

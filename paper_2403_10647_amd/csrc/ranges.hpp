@@ -1,0 +1,171 @@
+// Per-grid bookkeeping after the count, and the per-cell range table
+// (RunLengthEncode + NonEmptyCells + ExclusiveSum over the grid, Algorithm 1).
+//
+// The ranges are produced by a merge-path walk over two sorted sequences: the
+// cell events 0..R (event c stands for "cell c begins") and the sorted pair
+// cells, with an event ordered before the pairs of its own cell.  When event c
+// is reached, the number of pairs consumed so far is exactly the number of
+// pairs whose cell is < c, which is G[c].  Tiles split the merged sequence
+// evenly, so the work per tile is the same whether the cells are empty or
+// full; each event writes the begin of its cell and the end of the cell before
+// it, and the writes of a tile are one contiguous stretch of the table.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace gb {
+
+struct GridRun {
+  uint64_t pair_base;    // first pair of the grid in the batch's pair list
+  uint64_t npairs;       // NO of the grid
+  uint32_t mtile_base;   // first merge tile of the grid
+  uint32_t mtiles;       // merge tiles of the grid
+};
+
+// One workgroup: pair bases, pair counts and merge tiles of every grid.
+struct PlanArgs {
+  GridSet gs;
+  const uint32_t* start;   // [ntris]
+  uint32_t ntris;
+  uint32_t merge_tile;     // items per merge tile
+  GridRun* run;            // [ngrids + 1]; run[ngrids].mtile_base = total merge tiles
+  uint64_t* npairs_out;    // [ngrids] copy of each grid's NO for the host
+  uint32_t* cap_flag;      // set when a grid's NO exceeds its capacity
+  Control* ctl;
+};
+
+template <int Block, bool Batched>
+__global__ __launch_bounds__(Block) void plan_kernel(PlanArgs a) {
+  __shared__ uint32_t s_wtot[Block / kWave];
+  const uint64_t total = a.ctl->npairs;
+  const uint32_t G = a.gs.ngrids;
+  for (uint32_t g = threadIdx.x; g < G; g += Block) {
+    const uint32_t tb = grid_at<Batched>(a.gs, g).tri_base;
+    a.run[g].pair_base = tb < a.ntris ? a.start[tb] : total;
+  }
+  __syncthreads();
+  uint32_t carry = 0;
+  for (uint32_t g0 = 0; g0 < G; g0 += Block) {
+    const uint32_t g = g0 + threadIdx.x;
+    uint32_t tiles = 0;
+    if (g < G) {
+      const GridDev& gd = grid_at<Batched>(a.gs, g);
+      const uint64_t pb = a.run[g].pair_base;
+      const uint64_t pe = g + 1 < G ? a.run[g + 1].pair_base : total;
+      const uint64_t no = pe - pb;
+      const uint64_t ncell = static_cast<uint64_t>(gd.res[0]) * gd.res[1] * gd.res[2];
+      a.run[g].npairs = no;
+      if (a.npairs_out) a.npairs_out[g] = no;
+      if (no > gd.cap_pairs) atomicOr(a.cap_flag, 1u);
+      const uint64_t len = ncell + 1 + no;
+      tiles = static_cast<uint32_t>((len + a.merge_tile - 1) / a.merge_tile);
+      a.run[g].mtiles = tiles;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_sum<Block>(tiles, s_wtot, tot);
+    if (g < G) a.run[g].mtile_base = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) a.run[G].mtile_base = carry;
+}
+
+// Grid of merge tile b: largest g with run[g].mtile_base <= b.
+GB_DEV uint32_t grid_of_mtile(const GridRun* run, uint32_t ngrids, uint32_t b) {
+  uint32_t lo = 0, hi = ngrids;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (run[mid].mtile_base <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+struct RangesArgs {
+  GridSet gs;
+  const GridRun* run;
+  uint32_t* splits;        // [total merge tiles] pair index at each tile's start
+  uint32_t merge_tile;
+  Control* ctl;
+};
+
+// Merge-path split at diagonal d of grid g: the number of pairs among the
+// first d merged items = the smallest j with cells[j] + j + 1 >= d.
+GB_DEV uint32_t merge_split(const uint32_t* cells, uint64_t npairs, uint64_t nevents, uint64_t d) {
+  uint64_t lo = d > nevents ? d - nevents : 0;
+  uint64_t hi = d < npairs ? d : npairs;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (static_cast<uint64_t>(cells[mid]) + mid + 1 >= d) hi = mid; else lo = mid + 1;
+  }
+  return static_cast<uint32_t>(lo);
+}
+
+template <int Block, bool Batched>
+__global__ __launch_bounds__(Block) void split_kernel(RangesArgs a) {
+  const uint32_t G = a.gs.ngrids;
+  const uint32_t total = a.run[G].mtile_base;
+  for (uint32_t b = blockIdx.x * Block + threadIdx.x; b < total; b += gridDim.x * Block) {
+    const uint32_t g = Batched ? grid_of_mtile(a.run, G, b) : 0;
+    const GridDev& gd = grid_at<Batched>(a.gs, g);
+    const uint64_t ncell = static_cast<uint64_t>(gd.res[0]) * gd.res[1] * gd.res[2];
+    const uint64_t d = static_cast<uint64_t>(b - a.run[g].mtile_base) * a.merge_tile;
+    a.splits[b] = merge_split(gd.out_cells, a.run[g].npairs, ncell + 1, d);
+  }
+}
+
+template <int Block, int K, bool Batched>
+__global__ __launch_bounds__(Block) void ranges_kernel(RangesArgs a) {
+  constexpr int D = Block * K;
+  __shared__ uint32_t s_cells[D];
+  __shared__ uint32_t s_begin[D];
+  __shared__ uint32_t s_tile;
+  const uint32_t G = a.gs.ngrids;
+  const uint32_t total = a.run[G].mtile_base;
+  const uint32_t tid = threadIdx.x;
+  while (true) {
+    const uint32_t b = next_tile(&a.ctl->tile_counter[kCtrRanges], &s_tile);
+    if (b >= total) break;
+    const uint32_t g = Batched ? grid_of_mtile(a.run, G, b) : 0;
+    const GridDev& gd = grid_at<Batched>(a.gs, g);
+    const GridRun& gr = a.run[g];
+    const uint64_t ncell = static_cast<uint64_t>(gd.res[0]) * gd.res[1] * gd.res[2];
+    const uint64_t len = ncell + 1 + gr.npairs;
+    const uint32_t lb = b - gr.mtile_base;
+    const uint64_t d0 = static_cast<uint64_t>(lb) * D;
+    const uint64_t d1 = d0 + D < len ? d0 + D : len;
+    const uint64_t j0 = a.splits[b];
+    const uint64_t j1 = lb + 1 < gr.mtiles ? a.splits[b + 1] : gr.npairs;
+    const uint64_t i0 = d0 - j0, i1 = d1 - j1;
+    const uint32_t np = static_cast<uint32_t>(j1 - j0), ne = static_cast<uint32_t>(i1 - i0);
+    for (uint32_t p = tid; p < np; p += Block) s_cells[p] = gd.out_cells[j0 + p];
+    __syncthreads();
+    // this thread's stretch of the tile's diagonal
+    const uint32_t dd0 = tid * K;
+    const uint32_t nd = np + ne;
+    if (dd0 < nd) {
+      uint32_t lo = dd0 > ne ? dd0 - ne : 0, hi = dd0 < np ? dd0 : np;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (static_cast<uint64_t>(s_cells[mid]) + j0 + mid + 1 >= d0 + dd0) hi = mid; else lo = mid + 1;
+      }
+      uint32_t p = lo, e = dd0 - lo;
+      const uint32_t dend = dd0 + K < nd ? dd0 + K : nd;
+      for (uint32_t dd = dd0; dd < dend; ++dd) {
+        if (e < ne && (p >= np || i0 + e <= s_cells[p])) {
+          s_begin[e] = static_cast<uint32_t>(j0 + p);
+          ++e;
+        } else {
+          ++p;
+        }
+      }
+    }
+    __syncthreads();
+    // ranges[q] for q in [2 i0 - 1, 2 i1 - 1): q = 2c is begin(c), q = 2c - 1 is end(c - 1) = begin(c)
+    const uint64_t q0 = i0 > 0 ? 2 * i0 - 1 : 0;
+    const uint64_t q1e = 2 * i1 - 1;
+    const uint64_t q1 = q1e < 2 * ncell ? q1e : 2 * ncell;
+    for (uint64_t q = q0 + tid; q < q1; q += Block) gd.out_ranges[q] = s_begin[(q + 1) / 2 - i0];
+    __syncthreads();
+  }
+}
+
+}  // namespace gb

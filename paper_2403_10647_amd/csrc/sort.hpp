@@ -1,0 +1,245 @@
+// One pass of the LSD radix sort (RadixSort of Algorithm 1), in the
+// single-pass "onesweep" form (Adinets & Merrill): each tile ranks its keys by
+// one digit in LDS, obtains every digit's global offset by a decoupled
+// look-back over the tiles before it, and scatters through an LDS staging
+// buffer so each digit's run is written contiguously.
+#pragma once
+
+#include "ranges.hpp"
+
+namespace gb {
+
+enum SortSource : int { kFromArrays = 0, kFromExpansion = 1 };
+enum SortSink : int { kToArrays = 0, kToGrids = 1 };
+
+struct SortPassArgs {
+  const uint32_t* keys_in;  // kFromArrays
+  const uint32_t* vals_in;
+  uint32_t* keys_out;       // kToArrays
+  uint32_t* vals_out;
+  ExpandArgs ex;            // kFromExpansion (and grid table for kToGrids)
+  const uint32_t* hist;     // global digit histogram of this pass [radix]
+  uint64_t* status;         // [ntiles][radix] look-back words (zeroed)
+  uint64_t n;               // pairs, when not read from the control block
+  uint32_t n_from_ctl;      // 1: n = ctl->npairs
+  uint32_t shift;
+  uint32_t width;           // digit width of this pass (<= RB)
+  uint32_t counter;         // tile-counter slot
+  const GridRun* run;       // kToGrids: each grid's first pair
+  Control* ctl;
+};
+
+template <int Block, int K, int RB, int Source, int Sink, bool Batched>
+__global__ __launch_bounds__(Block) void onesweep_kernel(SortPassArgs a) {
+  constexpr int N = Block * K;
+  constexpr int R = 1 << RB;
+  constexpr int W = Block / kWave;
+  constexpr int DPT = R > Block ? R / Block : 1;        // digits per thread
+  static_assert(W * R * 4 <= N * 8, "wave counters must fit in the staging buffer");
+  // staging (keys then values) doubles as the per-wave digit counters and the
+  // expansion's owner slots
+  __shared__ uint32_t s_stage[2 * N];
+  __shared__ uint32_t s_tile_excl[R];
+  __shared__ uint32_t s_dst[R];
+  __shared__ uint32_t s_wtot[W];
+  __shared__ uint32_t s_tile;
+
+  const uint64_t n = a.n_from_ctl ? a.ctl->npairs : a.n;
+  const uint32_t ntiles = static_cast<uint32_t>((n + N - 1) / N);
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = lane_id();
+  const uint32_t w = tid / kWave;
+  const uint32_t dmask = (1u << a.width) - 1u;
+
+  while (true) {
+    const uint32_t tile = next_tile(&a.ctl->tile_counter[a.counter], &s_tile);
+    if (tile >= ntiles) break;
+    const uint64_t base = static_cast<uint64_t>(tile) * N;
+    const uint32_t nt = static_cast<uint32_t>(n - base < N ? n - base : N);
+
+    uint32_t keys[K], vals[K];
+    if constexpr (Source == kFromExpansion) {
+      expand_tile<Block, K, Batched>(a.ex, tile, n, ntiles, s_stage, s_wtot, keys, vals);
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const uint32_t idx = w * (kWave * K) + k * kWave + lane;
+        if (idx < nt) {
+          keys[k] = a.keys_in[base + idx];
+          vals[k] = a.vals_in[base + idx];
+        } else {
+          keys[k] = 0xFFFFFFFFu;
+          vals[k] = 0;
+        }
+      }
+    }
+
+    // ---- rank: per-wave digit counters, items of a wave taken in order ----
+    uint32_t* s_cnt = s_stage;  // [W][R]
+    for (int i = lane; i < R; i += kWave) s_cnt[w * R + i] = 0;
+    __builtin_amdgcn_wave_barrier();
+    uint32_t rank[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t idx = w * (kWave * K) + k * kWave + lane;
+      const bool valid = idx < nt;
+      const uint32_t d = (keys[k] >> a.shift) & dmask;
+      const uint64_t peers = match_digit<RB>(d, valid);
+      const uint32_t below = mbcnt(peers);
+      const uint32_t c = valid ? s_cnt[w * R + d] : 0u;
+      __builtin_amdgcn_wave_barrier();
+      if (valid && below == 0) s_cnt[w * R + d] = c + static_cast<uint32_t>(__builtin_popcountll(peers));
+      __builtin_amdgcn_wave_barrier();
+      rank[k] = c + below;
+    }
+    __syncthreads();
+
+    // ---- per digit: prefix over waves, tile total, publish aggregate ----
+    uint32_t dcount[DPT];
+    uint32_t tsum = 0;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+      const uint32_t d = tid * DPT + j;
+      uint32_t run = 0;
+      if (d < static_cast<uint32_t>(R)) {
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) {
+          const uint32_t c = s_cnt[ww * R + d];
+          s_cnt[ww * R + d] = run;
+          run += c;
+        }
+        if (tile == 0) {
+          // tile 0 starts each digit at the digit's global offset
+        } else {
+          status_store(a.status + static_cast<uint64_t>(tile) * R + d, kFlagAggregate, run);
+        }
+      }
+      dcount[j] = run;
+      tsum += run;
+    }
+    uint32_t ttot;
+    uint32_t texcl = block_exclusive_sum<Block>(tsum, s_wtot, ttot);
+    if (tile == 0) {
+      // global digit offsets: exclusive scan of the pass histogram
+      uint32_t hsum = 0, hv[DPT];
+#pragma unroll
+      for (int j = 0; j < DPT; ++j) {
+        const uint32_t d = tid * DPT + j;
+        hv[j] = d < static_cast<uint32_t>(R) ? a.hist[d] : 0u;
+        hsum += hv[j];
+      }
+      uint32_t htot;
+      uint32_t hex = block_exclusive_sum<Block>(hsum, s_wtot, htot);
+#pragma unroll
+      for (int j = 0; j < DPT; ++j) {
+        const uint32_t d = tid * DPT + j;
+        if (d < static_cast<uint32_t>(R)) {
+          status_store(a.status + d, kFlagPrefix, static_cast<uint64_t>(hex) + dcount[j]);
+          s_tile_excl[d] = texcl;
+          s_dst[d] = hex - texcl;
+        }
+        hex += hv[j];
+        texcl += dcount[j];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < DPT; ++j) {
+        const uint32_t d = tid * DPT + j;
+        if (d < static_cast<uint32_t>(R)) {
+          const uint64_t ex = lookback_thread(a.status, R, d, tile);
+          status_store(a.status + static_cast<uint64_t>(tile) * R + d, kFlagPrefix, ex + dcount[j]);
+          s_tile_excl[d] = texcl;
+          s_dst[d] = static_cast<uint32_t>(ex) - texcl;
+        }
+        texcl += dcount[j];
+      }
+    }
+    __syncthreads();
+
+    // ---- local positions, then stage keys and values in digit order ----
+    uint32_t pos[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t d = (keys[k] >> a.shift) & dmask;
+      pos[k] = s_tile_excl[d] + s_cnt[w * R + d] + rank[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t idx = w * (kWave * K) + k * kWave + lane;
+      if (idx < nt) {
+        s_stage[pos[k]] = keys[k];
+        s_stage[N + pos[k]] = vals[k];
+      }
+    }
+    __syncthreads();
+
+    // ---- scatter: consecutive threads write consecutive slots of a digit run ----
+    for (uint32_t i = tid; i < nt; i += Block) {
+      const uint32_t key = s_stage[i];
+      const uint32_t val = s_stage[N + i];
+      const uint32_t d = (key >> a.shift) & dmask;
+      const uint32_t dst = s_dst[d] + i;
+      if constexpr (Sink == kToArrays) {
+        a.keys_out[dst] = key;
+        a.vals_out[dst] = val;
+      } else {
+        const uint32_t g = key >> a.ex.gs.cell_bits;
+        const GridDev& G = a.ex.gs.table[g];
+        const uint64_t local = dst - a.run[g].pair_base;
+        G.out_cells[local] = key & ((1u << a.ex.gs.cell_bits) - 1u);
+        G.out_objs[local] = val;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Digit histograms of every pass from keys held in an array (one read).
+struct HistArrayArgs {
+  const uint32_t* keys;
+  uint64_t n;
+  SortPlan plan;
+  uint32_t* hist;           // [4][kRadixMax]
+  uint64_t* sort_status;    // [passes][status_stride], cleared here
+  uint64_t status_stride;
+  Control* ctl;
+};
+
+template <int Block, int K, int RB>
+__global__ __launch_bounds__(Block) void hist_array_kernel(HistArrayArgs a) {
+  constexpr int N = Block * K;
+  constexpr int R = 1 << RB;
+  __shared__ uint32_t s_hist[4 * R];
+  __shared__ uint32_t s_tile;
+  const uint32_t ntiles = static_cast<uint32_t>((a.n + N - 1) / N);
+  {
+    const uint64_t per_pass = static_cast<uint64_t>(ntiles) * R;
+    const uint64_t nwords = static_cast<uint64_t>(a.plan.passes) * per_pass;
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * Block + threadIdx.x; i < nwords;
+         i += static_cast<uint64_t>(gridDim.x) * Block)
+      a.sort_status[(i / per_pass) * a.status_stride + i % per_pass] = 0;
+  }
+  for (int i = threadIdx.x; i < 4 * R; i += Block) s_hist[i] = 0;
+  __syncthreads();
+  while (true) {
+    const uint32_t tile = next_tile(&a.ctl->tile_counter[kCtrHist], &s_tile);
+    if (tile >= ntiles) break;
+    const uint64_t base = static_cast<uint64_t>(tile) * N;
+    for (int k = 0; k < K; ++k) {
+      const uint64_t i = base + static_cast<uint64_t>(k) * Block + threadIdx.x;
+      if (i < a.n) {
+        const uint32_t key = a.keys[i];
+        for (uint32_t p = 0; p < a.plan.passes; ++p)
+          atomicAdd(&s_hist[p * R + ((key >> a.plan.shift[p]) & ((1u << a.plan.width[p]) - 1u))], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < a.plan.passes * R; i += Block) {
+    const uint32_t v = s_hist[i];
+    if (v) atomicAdd(&a.hist[(i / R) * kRadixMax + (i % R)], v);
+  }
+}
+
+}  // namespace gb
