@@ -121,6 +121,8 @@ int grid_expand(const float *verts_soa, uint32_t nverts, const uint32_t *tris, u
  * what grid_build returns for it alone: object ids local to the grid, ranges
  * relative to the grid's own pair list.  Pairs are sorted on a packed key
  * (grid index above the cell id) over only the bits in use. */
+/* Workspace for the batch as described (out.cap_pairs as set; output pointers
+ * may still be NULL when only counting).  0 if a descriptor is invalid. */
 size_t grid_workspace_size_batched(const grid_desc *grids, uint32_t ngrids);
 
 /* Per-grid NO into grids[g].out.npairs (host).  Synchronizes stream. */
@@ -155,6 +157,24 @@ enum { GRID_SCAN_EXCLUSIVE_SUM = 0, GRID_SCAN_INCLUSIVE_MAX = 1, GRID_SCAN_SEGME
 size_t grid_scan_workspace_size(uint64_t n);
 int grid_scan_u32(const uint32_t *in, const uint32_t *flags, uint32_t *out, uint64_t n, int op,
                   void *ws, size_t ws_bytes, uint64_t *total, void *stream);
+
+/* ---- kernel timing ------------------------------------------------------------ */
+
+/* Per-kernel totals collected while tracing is on. */
+typedef struct grid_trace_entry {
+  char name[48];       /* kernel: count_scan, plan, hist, onesweep_expand, onesweep, split, ranges, ... */
+  uint32_t launches;   /* launches since the last read */
+  double total_ms;     /* summed event-measured duration */
+} grid_trace_entry;
+
+/* Turn tracing on (1) or off (0) for the whole process.  While on, each kernel
+ * launch is bracketed by HIP events recorded on the launch's own stream. */
+int grid_trace_enable(int on);
+
+/* Wait for the traced launches, fold them into per-kernel totals and reset.
+ * Writes up to max_entries entries (host array) and *n_entries (host) = the
+ * number of distinct kernels seen. */
+int grid_trace_read(grid_trace_entry *out, int max_entries, int *n_entries);
 
 #ifdef __cplusplus
 }

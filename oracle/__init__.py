@@ -165,24 +165,36 @@ def build_stages(verts, tris, lo, hi, res, keep_objorder: bool = True) -> Oracle
     return OracleGrid(box_lo, box_m, count, start, no, c0, o0, cells, objs, rg)
 
 
-def build(verts, tris, lo, hi, res):
-    """Whole build in one C call: (cells, objs, ranges) sorted by cell."""
+def probe_npairs(verts, tris, lo, hi, res) -> int:
+    """NO of the grid, without building it."""
     verts = np.ascontiguousarray(verts, np.float32)
     tris = np.ascontiguousarray(tris, np.uint32)
     lo, hi, res = _grid_args(lo, hi, res)
-    ncells = int(np.prod(res.astype(np.int64)))
     npairs = np.zeros(1, np.uint64)
-    z = np.zeros(1, np.uint32)
     st = lib().oracle_build(_p(verts), verts.shape[1], _p(tris), tris.shape[0], _p(lo), _p(hi), _p(res),
-                            _p(z), _p(z), _p(z), 0, _p(npairs))
-    if st not in (0, -4):
+                            None, None, None, 0, _p(npairs))
+    if st != 0:
         raise OracleError(st)
-    no = int(npairs[0])
+    return int(npairs[0])
+
+
+def build(verts, tris, lo, hi, res, npairs=None):
+    """Whole build in one C call: (cells, objs, ranges) sorted by cell.
+
+    ``npairs`` (from probe_npairs) sizes the outputs; it is probed if absent."""
+    verts = np.ascontiguousarray(verts, np.float32)
+    tris = np.ascontiguousarray(tris, np.uint32)
+    lo, hi, res = _grid_args(lo, hi, res)
+    if npairs is None:
+        npairs = probe_npairs(verts, tris, lo, hi, res)
+    no = int(npairs)
+    ncells = int(np.prod(res.astype(np.int64)))
     cells = np.zeros(max(no, 1), np.uint32)
     objs = np.zeros(max(no, 1), np.uint32)
     rg = np.zeros(2 * ncells, np.uint32)
+    got = np.zeros(1, np.uint64)
     st = lib().oracle_build(_p(verts), verts.shape[1], _p(tris), tris.shape[0], _p(lo), _p(hi), _p(res),
-                            _p(cells), _p(objs), _p(rg), no, _p(npairs))
+                            _p(cells), _p(objs), _p(rg), no, _p(got))
     if st != 0:
         raise OracleError(st)
     return cells[:no], objs[:no], rg

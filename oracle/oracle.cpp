@@ -169,7 +169,8 @@ void oracle_ranges(uint64_t npairs, const uint32_t* sorted_cells, uint64_t ncell
 
 // Whole build: BuildParallelGrid(M, boxes) -> (G, O), plus the sorted C.
 // cells/objs hold cap_pairs entries and ranges 2 * ncells; when NO exceeds
-// cap_pairs only *npairs is written and -4 (capacity) is returned.
+// cap_pairs only *npairs is written and -4 (capacity) is returned.  With
+// ranges == nullptr the call only reports *npairs (a sizing probe).
 int oracle_build(const float* verts_soa, uint32_t nverts, const uint32_t* tris, uint32_t ntris,
                  const float lo[3], const float hi[3], const uint32_t res[3],
                  uint32_t* cells, uint32_t* objs, uint32_t* ranges, uint64_t cap_pairs, uint64_t* npairs) {
@@ -180,6 +181,7 @@ int oracle_build(const float* verts_soa, uint32_t nverts, const uint32_t* tris, 
   uint64_t no = oracle_exclusive_sum(count.data(), ntris, start.data());
   *npairs = no;
   if (no > 0xFFFFFFFFull) return kOverflow;
+  if (ranges == nullptr) return kOk;
   if (no > cap_pairs) return kCapacity;
   oracle_make_pairs(ntris, box_lo.data(), box_m.data(), count.data(), res, cells, objs);
   oracle_sort_pairs(no, cells, objs);

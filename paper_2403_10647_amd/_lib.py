@@ -34,6 +34,7 @@ EXPORTS = (
     "grid_strerror", "grid_workspace_size", "grid_count", "grid_build", "grid_expand",
     "grid_workspace_size_batched", "grid_count_batched", "grid_build_batched",
     "grid_sort_workspace_size", "grid_sort_pairs", "grid_scan_workspace_size", "grid_scan_u32",
+    "grid_trace_enable", "grid_trace_read",
 )
 
 
@@ -47,6 +48,10 @@ class GridError(RuntimeError):
 class grid_out(C.Structure):
     _fields_ = [("cells", C.c_void_p), ("objs", C.c_void_p), ("ranges", C.c_void_p),
                 ("cap_pairs", C.c_uint64), ("npairs", C.c_uint64)]
+
+
+class grid_trace_entry(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_uint32), ("total_ms", C.c_double)]
 
 
 class grid_desc(C.Structure):
@@ -88,7 +93,9 @@ def lib():
         L.grid_scan_workspace_size.argtypes = [U64]
         L.grid_scan_workspace_size.restype = SZ
         L.grid_scan_u32.argtypes = [P, P, P, U64, C.c_int, P, SZ, C.POINTER(C.c_uint64), P]
-        for name in ("grid_count", "grid_build", "grid_expand", "grid_count_batched", "grid_build_batched",
+        L.grid_trace_enable.argtypes = [C.c_int]
+        L.grid_trace_read.argtypes = [C.POINTER(grid_trace_entry), C.c_int, C.POINTER(C.c_int)]
+        for name in ("grid_trace_enable", "grid_trace_read", "grid_count", "grid_build", "grid_expand", "grid_count_batched", "grid_build_batched",
                      "grid_sort_pairs", "grid_scan_u32"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -324,3 +331,15 @@ def scan_u32(x: torch.Tensor, op: int, flags: Optional[torch.Tensor] = None, ws:
                          C.c_void_p(out.data_ptr()), n, op, wp, wn, C.byref(tot), _stream(stream))
     _check(st, "grid_scan_u32")
     return out, int(tot.value)
+
+
+def trace_enable(on: bool = True):
+    _check(lib().grid_trace_enable(1 if on else 0), "grid_trace_enable")
+
+
+def trace_read() -> dict:
+    """{kernel: (launches, total_ms)} since the last read (waits for the launches)."""
+    arr = (grid_trace_entry * 64)()
+    n = C.c_int(0)
+    _check(lib().grid_trace_read(arr, 64, C.byref(n)), "grid_trace_read")
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(n.value, 64))}

@@ -61,6 +61,58 @@ int device_cus() {
   return cache[dev];
 }
 
+// ---- optional per-kernel timing --------------------------------------------------
+// When enabled, every launch is bracketed by a pair of HIP events recorded on
+// the launch's own stream; grid_trace_read() folds them into per-kernel totals.
+struct TraceRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+struct Tracer {
+  std::mutex mu;
+  bool on = false;
+  std::vector<TraceRec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Tracer& tracer() {
+  static Tracer t;
+  return t;
+}
+
+class TraceScope {
+ public:
+  TraceScope(hipStream_t s, const char* name) : s_(s) {
+    Tracer& t = tracer();
+    if (!t.on) return;
+    std::lock_guard<std::mutex> lock(t.mu);
+    rec_.name = name;
+    rec_.a = t.get();
+    rec_.b = t.get();
+    if (rec_.a && rec_.b && hipEventRecord(rec_.a, s_) == hipSuccess) active_ = true;
+  }
+  ~TraceScope() {
+    if (!active_) return;
+    Tracer& t = tracer();
+    std::lock_guard<std::mutex> lock(t.mu);
+    if (hipEventRecord(rec_.b, s_) == hipSuccess) t.recs.push_back(rec_);
+  }
+
+ private:
+  hipStream_t s_;
+  TraceRec rec_{};
+  bool active_ = false;
+};
+
 // ---- radix-sort plan ----------------------------------------------------------
 struct Plan {
   SortPlan sp;
@@ -91,7 +143,7 @@ Plan make_plan(uint32_t bits, int max_digit = -1) {
 // ---- workspace layout -----------------------------------------------------------
 struct Layout {
   size_t ctl, hist, count_status, zero_end;
-  size_t start, box, tfo, sort_status, keys_alt, vals_alt, run, npairs_out, splits, table, total;
+  size_t start, box, tfo, sort_status, keys_alt, vals_alt, keys_alt2, vals_alt2, run, npairs_out, splits, table, total;
   uint32_t ntfo, ncount_tiles, nsort_tiles_cap, nmerge_tiles_cap;
 };
 
@@ -118,6 +170,10 @@ Layout make_layout(uint64_t ntris, uint64_t cap_pairs, uint64_t ncells_plus_grid
   L.sort_status = take(static_cast<size_t>(plan.sp.passes) * L.nsort_tiles_cap * (size_t{1} << plan.rb) * 8);
   L.keys_alt = take(cap_pairs * 4);
   L.vals_alt = take(cap_pairs * 4);
+  // batched builds scatter their last pass into per-grid outputs, so the
+  // passes before it ping-pong between two workspace buffers
+  L.keys_alt2 = take(batched ? cap_pairs * 4 : 0);
+  L.vals_alt2 = take(batched ? cap_pairs * 4 : 0);
   L.run = take((ngrids + 1) * sizeof(GridRun));
   L.npairs_out = take(ngrids * 8);
   L.splits = take(static_cast<size_t>(L.nmerge_tiles_cap) * 4);
@@ -171,6 +227,7 @@ __global__ void zero_kernel(uint64_t* p, uint64_t nwords) {
 int launch_zero(void* ws, size_t bytes, hipStream_t s) {
   const uint64_t words = bytes / 8;
   const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>(ceil_div(words, 256), 1024));
+  TraceScope ts(s, "zero");
   zero_kernel<<<std::max(blocks, 1u), 256, 0, s>>>(static_cast<uint64_t*>(ws), words);
   GB_LAUNCHED();
   return GRID_OK;
@@ -199,6 +256,7 @@ int launch_count(Build& b) {
   a.sort_tile_shift = kSortTileShift;
   a.status = at<uint64_t>(b.ws, b.L.count_status);
   a.ctl = at<Control>(b.ws, b.L.ctl);
+  TraceScope ts(b.s, "count_scan");
   count_kernel<kCountBlock, kCountK, B><<<b.L.ncount_tiles, kCountBlock, 0, b.s>>>(a);
   GB_LAUNCHED();
   return GRID_OK;
@@ -215,6 +273,7 @@ int launch_plan(Build& b) {
   a.npairs_out = at<uint64_t>(b.ws, b.L.npairs_out);
   a.cap_flag = &at<Control>(b.ws, b.L.ctl)->pad0;
   a.ctl = at<Control>(b.ws, b.L.ctl);
+  TraceScope ts(b.s, "plan");
   plan_kernel<kPlanBlock, B><<<1, kPlanBlock, 0, b.s>>>(a);
   GB_LAUNCHED();
   return GRID_OK;
@@ -243,6 +302,7 @@ int launch_expand(Build& b, uint32_t* cells, uint32_t* objs, uint64_t npairs) {
   a.cells = cells;
   a.objs = objs;
   a.ctl = at<Control>(b.ws, b.L.ctl);
+  TraceScope ts(b.s, "expand");
   expand_kernel<kSortBlock, kSortK, B><<<persistent_blocks(ceil_div(npairs, kSortTile), 4), kSortBlock, 0, b.s>>>(a);
   GB_LAUNCHED();
   return GRID_OK;
@@ -261,19 +321,31 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
     h.sort_status = at<uint64_t>(b.ws, b.L.sort_status);
     h.status_stride = static_cast<uint64_t>(b.L.nsort_tiles_cap) * (1u << RB);
     h.ctl = ctl;
+    TraceScope ts(b.s, "hist");
     hist_kernel<kSortBlock, kSortK, RB, B><<<persistent_blocks(ntiles, 3), kSortBlock, 0, b.s>>>(h);
     GB_LAUNCHED();
   }
   uint32_t* alt_k = at<uint32_t>(b.ws, b.L.keys_alt);
   uint32_t* alt_v = at<uint32_t>(b.ws, b.L.vals_alt);
+  uint32_t* alt2_k = at<uint32_t>(b.ws, b.L.keys_alt2);
+  uint32_t* alt2_v = at<uint32_t>(b.ws, b.L.vals_alt2);
   const uint32_t P = sp.passes;
   const uint32_t blocks = persistent_blocks(ntiles, 2);
   const uint32_t* in_k = nullptr;
   const uint32_t* in_v = nullptr;
   for (uint32_t p = 0; p < P; ++p) {
-    const bool to_out = ((P - 1 - p) % 2) == 0;
-    uint32_t* ok = to_out ? out_cells : alt_k;
-    uint32_t* ov = to_out ? out_objs : alt_v;
+    uint32_t* ok;
+    uint32_t* ov;
+    if (B) {
+      // the last pass writes each grid's own outputs; earlier ones alternate
+      ok = p + 1 == P ? nullptr : (p % 2 == 0 ? alt_k : alt2_k);
+      ov = p + 1 == P ? nullptr : (p % 2 == 0 ? alt_v : alt2_v);
+    } else {
+      const bool to_out = ((P - 1 - p) % 2) == 0;
+      ok = to_out ? out_cells : alt_k;
+      ov = to_out ? out_objs : alt_v;
+    }
+    if ((!B || p + 1 < P) && (!ok || !ov)) return GRID_E_INVAL;  // never launch a pass without a destination
     SortPassArgs a{};
     a.keys_in = in_k;
     a.vals_in = in_v;
@@ -290,6 +362,7 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
     a.run = at<GridRun>(b.ws, b.L.run);
     a.ctl = ctl;
     const bool last = p + 1 == P;
+    TraceScope ts(b.s, p == 0 ? "onesweep_expand" : "onesweep");
     if (p == 0) {
       if (B && last)
         onesweep_kernel<kSortBlock, kSortK, RB, kFromExpansion, kToGrids, B><<<blocks, kSortBlock, 0, b.s>>>(a);
@@ -328,9 +401,13 @@ int launch_ranges(Build& b, uint64_t merge_items_cap) {
   a.merge_tile = kMergeTile;
   a.ctl = at<Control>(b.ws, b.L.ctl);
   const uint64_t tiles = ceil_div(merge_items_cap, kMergeTile) + b.gs.ngrids;
+  {
+  TraceScope ts(b.s, "split");
   split_kernel<256, B><<<static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(tiles, 256), 4096))),
                          256, 0, b.s>>>(a);
   GB_LAUNCHED();
+  }
+  TraceScope ts(b.s, "ranges");
   ranges_kernel<kRangesBlock, kRangesK, B><<<persistent_blocks(tiles, 8), kRangesBlock, 0, b.s>>>(a);
   GB_LAUNCHED();
   return GRID_OK;
@@ -500,7 +577,7 @@ int setup_batch(const grid_desc* grids, uint32_t ngrids, BatchSetup* bs, bool ne
     gd.cell_base = bs->cells;
     bs->table[g] = gd;
     bs->ntris += d.ntris;
-    bs->cap += need_out ? d.out.cap_pairs : 0;
+    bs->cap += d.out.cap_pairs;
     bs->cells += ncells_of(d.res);
     bs->cell_bits = std::max(bs->cell_bits, bits_for(ncells_of(d.res)));
   }
@@ -568,10 +645,13 @@ size_t batched_ws_one(const grid_desc* grids, uint32_t ngrids, bool need_out) {
 extern "C" {
 
 size_t grid_workspace_size_batched(const grid_desc* grids, uint32_t ngrids) {
+  if (!grids) return 0;
   size_t need = 0;
   for (uint32_t g0 = 0; g0 < ngrids;) {
     const uint32_t n = batch_chunk(grids, ngrids, g0);
-    need = std::max(need, batched_ws_one(grids + g0, n, true));
+    const size_t one = batched_ws_one(grids + g0, n, false);
+    if (one == 0) return 0;
+    need = std::max(need, one);
     g0 += n;
   }
   return need;
@@ -665,6 +745,7 @@ int sort_arrays_rb(uint32_t* keys, uint32_t* vals, uint32_t* ka, uint32_t* va, u
     h.sort_status = at<uint64_t>(ws, L.status);
     h.status_stride = stride;
     h.ctl = ctl;
+    TraceScope ts(s, "hist_array");
     hist_array_kernel<kSortBlock, kSortK, RB><<<persistent_blocks(L.ntiles, 3), kSortBlock, 0, s>>>(h);
     GB_LAUNCHED();
   }
@@ -686,6 +767,7 @@ int sort_arrays_rb(uint32_t* keys, uint32_t* vals, uint32_t* ka, uint32_t* va, u
     a.width = plan.sp.width[p];
     a.counter = kCtrSort0 + p;
     a.ctl = ctl;
+    TraceScope ts(s, "onesweep");
     onesweep_kernel<kSortBlock, kSortK, RB, kFromArrays, kToArrays, false>
         <<<persistent_blocks(L.ntiles, 2), kSortBlock, 0, s>>>(a);
     GB_LAUNCHED();
@@ -768,6 +850,48 @@ int grid_scan_u32(const uint32_t* in, const uint32_t* flags, uint32_t* out, uint
   if (op == GRID_SCAN_SEGMENTED_EXCLUSIVE_SUM) t &= ScanSeg::kSum;
   *total = t;
   return GRID_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// Kernel timing.
+// ---------------------------------------------------------------------------------
+extern "C" {
+
+int grid_trace_enable(int on) {
+  Tracer& t = tracer();
+  std::lock_guard<std::mutex> lock(t.mu);
+  t.on = on != 0;
+  return GRID_OK;
+}
+
+int grid_trace_read(grid_trace_entry* out, int max_entries, int* n_entries) {
+  if (!n_entries || (max_entries > 0 && !out)) return GRID_E_INVAL;
+  Tracer& t = tracer();
+  std::lock_guard<std::mutex> lock(t.mu);
+  std::vector<grid_trace_entry> agg;
+  int status = GRID_OK;
+  for (TraceRec& r : t.recs) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) status = GRID_E_HIP;
+    grid_trace_entry* e = nullptr;
+    for (auto& x : agg)
+      if (std::strncmp(x.name, r.name, sizeof(x.name)) == 0) e = &x;
+    if (!e) {
+      agg.push_back(grid_trace_entry{});
+      e = &agg.back();
+      std::strncpy(e->name, r.name, sizeof(e->name) - 1);
+    }
+    e->launches += 1;
+    e->total_ms += ms;
+    t.pool.push_back(r.a);
+    t.pool.push_back(r.b);
+  }
+  t.recs.clear();
+  *n_entries = static_cast<int>(agg.size());
+  for (int i = 0; i < static_cast<int>(agg.size()) && i < max_entries; ++i) out[i] = agg[i];
+  return status;
 }
 
 }  // extern "C"

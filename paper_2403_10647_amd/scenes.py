@@ -82,8 +82,14 @@ def soup_from_vertices(v: np.ndarray):
 
 
 def aabb_bounds(verts: np.ndarray):
-    """FP32 axis-aligned bounding box of all vertices (the grid bounds)."""
-    return (verts.min(axis=1).astype(np.float32), verts.max(axis=1).astype(np.float32))
+    """FP32 axis-aligned bounding box of all vertices (the grid bounds); the unit
+    cube when there are none, and never empty along an axis."""
+    if verts.shape[1] == 0:
+        return np.zeros(3, np.float32), np.ones(3, np.float32)
+    lo = verts.min(axis=1).astype(np.float32)
+    hi = verts.max(axis=1).astype(np.float32)
+    hi = np.where(hi > lo, hi, np.nextafter(lo, np.float32(np.inf))).astype(np.float32)
+    return lo, hi
 
 
 def resolution_rule(lo, hi, ntris: int, lam: float, cap: int) -> np.ndarray:
@@ -159,21 +165,24 @@ def _arch_scene(seed: int, ntris: int = 10_000_000, nwalls: int = 10_000,
         q[:, 3, a1], q[:, 3, a2] = c1, e2
         quads[sel] = q
     walls = np.concatenate([quads[:, [0, 1, 2]], quads[:, [0, 2, 3]]], axis=0)
-    # Clusters of tiny triangles around Gaussian centres.
-    ncl = ntris - walls.shape[0]
+    # Clusters of tiny triangles around Gaussian centres; every triangle lands
+    # at a random position of the soup (walls interleaved with clutter).
+    nw = walls.shape[0]
+    ncl = ntris - nw
+    perm = rng.permutation(ntris)
+    soup = np.empty((ntris, 3, 3), np.float32)
+    soup[perm[:nw]] = walls
     centres = rng.uniform(0.0, 1.0, size=(nclusters, 3)) * box
-    which = rng.integers(0, nclusters, size=ncl)
-    v = np.empty((ncl, 3, 3), np.float64)
     chunk = 1 << 20
     for s in range(0, ncl, chunk):
         e = min(ncl, s + chunk)
         n = e - s
-        cen = centres[which[s:e]] + rng.normal(0.0, 0.5, size=(n, 3))
+        which = rng.integers(0, nclusters, size=n)
+        cen = centres[which] + rng.normal(0.0, 0.5, size=(n, 3))
         r = rng.lognormal(math.log(0.02), 0.5, size=(n, 3, 1))
-        v[s:e] = cen[:, None, :] + r * _unit_sphere(rng, (n, 3))
-    allv = np.concatenate([walls, v], axis=0)
-    allv = allv[rng.permutation(allv.shape[0])]
-    verts, tris = soup_from_vertices(allv)
+        soup[perm[nw + s:nw + e]] = cen[:, None, :] + r * _unit_sphere(rng, (n, 3))
+    verts, tris = soup_from_vertices(soup)
+    del soup
     lo, hi = aabb_bounds(verts)
     return Scene("arch", verts, tris, lo, hi, resolution_rule(lo, hi, ntris, lam, cap), seed)
 

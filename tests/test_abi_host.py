@@ -1,0 +1,132 @@
+"""Host-side checks of the C ABI that need no GPU.
+
+The library loads on a machine without a GPU; every function declared in
+include/gridbuild.h is exported; and argument validation, workspace sizing and
+error strings are host logic that runs before any device call.
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+torch = pytest.importorskip("torch")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gridbuild.h")
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_2403_10647_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2403_10647_amd import build
+        build.build()
+    _lib.lib()
+    return _lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(grid_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported(G):
+    names = declared_functions()
+    assert len(names) >= 14
+    L = G.lib()
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in gridbuild.h but not exported"
+    assert set(names) == set(G.EXPORTS)
+
+
+def test_strerror(G):
+    L = G.lib()
+    for st in (0, -1, -2, -3, -4, -5, -6):
+        assert L.grid_strerror(st)
+    assert L.grid_strerror(-4) == b"pair capacity too small"
+    assert L.grid_strerror(12345) == b"unknown status"
+
+
+def test_workspace_sizes_grow(G):
+    a = G.workspace_size(1000, 4000, [32, 32, 32])
+    b = G.workspace_size(1000, 400000, [32, 32, 32])
+    c = G.workspace_size(100000, 400000, [32, 32, 32])
+    assert 0 < a < b < c
+    L = G.lib()
+    assert L.grid_sort_workspace_size(1 << 20, 25) > L.grid_sort_workspace_size(1 << 20, 8) > 0
+    assert L.grid_sort_workspace_size(10, 33) == 0
+    assert L.grid_scan_workspace_size(1 << 20) > L.grid_scan_workspace_size(10) > 0
+
+
+def _args(G, lo=(0, 0, 0), hi=(1, 1, 1), res=(4, 4, 4)):
+    return (C.c_void_p(16), C.c_uint32(3), C.c_void_p(16), C.c_uint32(1), G._f3(lo), G._f3(hi), G._u3(res))
+
+
+@pytest.mark.parametrize("lo,hi,res", [
+    ((0, 0, 0), (0, 1, 1), (4, 4, 4)),          # lo == hi
+    ((0, 2, 0), (1, 1, 1), (4, 4, 4)),          # lo > hi
+    ((0, 0, 0), (1, 1, 1), (0, 4, 4)),          # res 0
+    ((0, 0, 0), (1, 1, 1), (4, 4, 1025)),       # res above 1024
+    ((float("nan"), 0, 0), (1, 1, 1), (4, 4, 4)),
+    ((0, 0, 0), (float("inf"), 1, 1), (4, 4, 4)),
+])
+def test_invalid_grids_rejected_on_host(G, lo, hi, res):
+    L = G.lib()
+    out = G.grid_out(16, 16, 16, 10, 0)
+    st = L.grid_build(*_args(G, lo, hi, res), C.c_void_p(16), 1 << 30, C.byref(out), None)
+    assert st == G.GRID_E_INVAL
+    no = C.c_uint64(0)
+    st = L.grid_count(*_args(G, lo, hi, res), C.c_void_p(16), 1 << 30, None, C.byref(no), None)
+    assert st == G.GRID_E_INVAL
+
+
+def test_null_and_small_workspace_rejected(G):
+    L = G.lib()
+    out = G.grid_out(16, 16, 16, 10, 0)
+    assert L.grid_build(*_args(G), None, 1 << 30, C.byref(out), None) == G.GRID_E_INVAL
+    assert L.grid_build(*_args(G), C.c_void_p(16), 64, C.byref(out), None) == G.GRID_E_NOMEM
+    bad = G.grid_out(16, 0, 16, 10, 0)         # objs missing
+    assert L.grid_build(*_args(G), C.c_void_p(16), 1 << 30, C.byref(bad), None) == G.GRID_E_INVAL
+    assert L.grid_build(*_args(G), C.c_void_p(16), 1 << 30, None, None) == G.GRID_E_INVAL
+    no = C.c_uint64(0)
+    assert L.grid_count(*_args(G), C.c_void_p(16), 1 << 30, None, None, None) == G.GRID_E_INVAL
+
+
+def test_primitives_validate_on_host(G):
+    L = G.lib()
+    tot = C.c_uint64(7)
+    P = C.c_void_p(16)
+    assert L.grid_scan_u32(P, None, P, 10, 3, P, 1 << 20, C.byref(tot), None) == G.GRID_E_INVAL
+    assert L.grid_scan_u32(P, None, P, 10, 2, P, 1 << 20, C.byref(tot), None) == G.GRID_E_INVAL  # flags missing
+    assert L.grid_scan_u32(P, None, P, 0, 0, P, 1 << 20, C.byref(tot), None) == G.GRID_OK and tot.value == 0
+    assert L.grid_scan_u32(P, None, P, 1000, 0, P, 8, C.byref(tot), None) == G.GRID_E_NOMEM
+    assert L.grid_sort_pairs(P, P, P, P, 10, 33, P, 1 << 20, None) == G.GRID_E_INVAL
+    assert L.grid_sort_pairs(P, P, P, P, 0, 16, P, 1 << 20, None) == G.GRID_OK
+    assert L.grid_sort_pairs(P, P, P, P, 10, 0, P, 1 << 20, None) == G.GRID_OK
+    assert L.grid_sort_pairs(P, P, P, P, 100000, 16, P, 64, None) == G.GRID_E_NOMEM
+
+
+def test_batched_validation_on_host(G):
+    L = G.lib()
+    assert L.grid_build_batched(None, 0, C.c_void_p(16), 1 << 20, None) == G.GRID_E_INVAL
+    arr = (G.grid_desc * 2)()
+    for d in arr:
+        d.verts_soa, d.tris, d.nverts, d.ntris = 16, 16, 3, 1
+        d.lo[:] = [0, 0, 0]
+        d.hi[:] = [1, 1, 1]
+        d.res[:] = [4, 4, 4]
+        d.out.cells, d.out.objs, d.out.ranges, d.out.cap_pairs = 16, 16, 16, 4
+    arr[1].res[:] = [4, 0, 4]
+    assert L.grid_workspace_size_batched(arr, 2) == 0
+    assert L.grid_build_batched(arr, 2, C.c_void_p(16), 1 << 20, None) == G.GRID_E_INVAL
+    arr[1].res[:] = [4, 4, 4]
+    assert L.grid_workspace_size_batched(arr, 2) > 0
+    assert L.grid_build_batched(arr, 2, C.c_void_p(16), 64, None) == G.GRID_E_NOMEM
+
+
+def test_trace_read_without_launches(G):
+    G.trace_enable(True)
+    assert G.trace_read() == {}
+    G.trace_enable(False)

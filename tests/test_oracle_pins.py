@@ -303,3 +303,14 @@ def test_stats_from_ranges():
     assert math.isclose(row["avg_cells_per_item"], g.npairs / 4096)
     assert row["max_cells_per_item"] == int(g.count.max())
     assert math.isclose(row["memory_MiB"], 4 * (32768 + g.npairs) / 2 ** 20)
+
+
+def test_probe_writes_nothing_and_empty_scene():
+    # the sizing probe only reports NO; an empty scene builds to all-empty ranges
+    verts, tris = np.zeros((3, 0), np.float32), np.zeros((0, 3), np.uint32)
+    lo, hi, res = np.zeros(3, np.float32), np.ones(3, np.float32), np.array([2, 2, 7], np.uint32)
+    assert oracle.probe_npairs(verts, tris, lo, hi, res) == 0
+    c, o, r = oracle.build(verts, tris, lo, hi, res)
+    assert len(c) == 0 and len(o) == 0 and r.shape == (56,) and not r.any()
+    v2, t2 = _soup([[[0.1, 0.1, 0.1], [0.9, 0.9, 0.9], [0.5, 0.5, 0.5]]])
+    assert oracle.probe_npairs(v2, t2, lo, hi, res) == 2 * 2 * 7
