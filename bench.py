@@ -33,6 +33,7 @@ def kernel_bytes(name: str, T: int, NO: int, R: int) -> float:
     """Algorithmic bytes one launch of `name` must move (see the design doc for the model)."""
     return {
         "count_scan": 60.0 * T,            # 12 B indices + 36 B vertices in, 4 B start + 8 B box out
+        "expand_hist": 12.0 * T + 8.0 * NO,  # start + box in, object-order pairs out
         "hist": 12.0 * T,                  # start + box of every object, keys regenerated
         "onesweep_expand": 12.0 * T + 8.0 * NO,  # regenerated keys in, pairs out
         "onesweep": 16.0 * NO,             # pairs in, pairs out
@@ -142,6 +143,8 @@ def main():
     ap.add_argument("--ngrids", type=int, default=512)
     ap.add_argument("--no-trace", action="store_true", help="time without per-kernel events")
     ap.add_argument("--mode", default="bench", choices=["bench", "copy"])
+    ap.add_argument("--max-digit-bits", type=int, default=None, help="override the radix digit width")
+    ap.add_argument("--fused", type=int, default=None, choices=[0, 1], help="first radix pass regenerates keys")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -160,6 +163,11 @@ def main():
 
     G.lib()
     torch.cuda.set_device(0)
+    if args.max_digit_bits is not None:
+        G.tune_set("max_digit_bits", args.max_digit_bits)
+    if args.fused is not None:
+        G.tune_set("fused_expand", args.fused)
+    knobs = {"max_digit_bits": G.tune_get("max_digit_bits"), "fused_expand": G.tune_get("fused_expand")}
     t0 = time.time()
     scene = scenes.make_scene(args.workload, seed=args.seed)
     gin = G.GridInput.from_scene(scene)
@@ -233,7 +241,7 @@ def main():
                     "100x10x100 box, lambda=2, cap 1024",
             "mixed": "1M triangles, 95% small / 5% large, lambda=4, cap 512",
             "small": "4096 small triangles, 32^3 grid"}[args.workload],
-                   "triangles": T, "npairs": NO, "res": [int(x) for x in scene.res], "cells": R, "seed": args.seed,
+                   "knobs": knobs, "triangles": T, "npairs": NO, "res": [int(x) for x in scene.res], "cells": R, "seed": args.seed,
                    "table1": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in row.items()
                               if k not in ("max_cells_per_item",)}},
         "event_ms_per_build": round(ev0.elapsed_time(ev1) / args.steps, 4),

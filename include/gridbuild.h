@@ -158,6 +158,23 @@ size_t grid_scan_workspace_size(uint64_t n);
 int grid_scan_u32(const uint32_t *in, const uint32_t *flags, uint32_t *out, uint64_t n, int op,
                   void *ws, size_t ws_bytes, uint64_t *total, void *stream);
 
+/* ---- tuning ------------------------------------------------------------------- */
+
+/* Process-wide knobs (not thread-safe against concurrent builds; set them
+ * before building).  Keys:
+ *   "max_digit_bits"  widest radix digit a sort pass may use, 4..11 (default 9):
+ *                     a b-bit key is sorted in ceil(b / max) passes of equal width
+ *   "fused_expand"    1: the first radix pass regenerates its keys from the
+ *                     expansion instead of reading them (default 0)
+ * Outputs never depend on the knobs.  GRID_E_INVAL for an unknown key or value. */
+int grid_tune_set(const char *key, int value);
+int grid_tune_get(const char *key, int *value);
+
+/* The radix plan a key of nbits bits gets under the current knobs: *passes
+ * (host) passes (at most 4) of widths[0..passes) bits, lowest digit first,
+ * run by the kernel built for *kernel_digit_bits-bit digits. */
+int grid_sort_plan(uint32_t nbits, uint32_t *passes, uint32_t widths[4], uint32_t *kernel_digit_bits);
+
 /* ---- kernel timing ------------------------------------------------------------ */
 
 /* Per-kernel totals collected while tracing is on. */

@@ -34,7 +34,7 @@ EXPORTS = (
     "grid_strerror", "grid_workspace_size", "grid_count", "grid_build", "grid_expand",
     "grid_workspace_size_batched", "grid_count_batched", "grid_build_batched",
     "grid_sort_workspace_size", "grid_sort_pairs", "grid_scan_workspace_size", "grid_scan_u32",
-    "grid_trace_enable", "grid_trace_read",
+    "grid_trace_enable", "grid_trace_read", "grid_tune_set", "grid_tune_get", "grid_sort_plan",
 )
 
 
@@ -93,6 +93,12 @@ def lib():
         L.grid_scan_workspace_size.argtypes = [U64]
         L.grid_scan_workspace_size.restype = SZ
         L.grid_scan_u32.argtypes = [P, P, P, U64, C.c_int, P, SZ, C.POINTER(C.c_uint64), P]
+        L.grid_tune_set.argtypes = [C.c_char_p, C.c_int]
+        L.grid_tune_get.argtypes = [C.c_char_p, C.POINTER(C.c_int)]
+        L.grid_tune_set.restype = C.c_int
+        L.grid_sort_plan.argtypes = [U32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+        L.grid_sort_plan.restype = C.c_int
+        L.grid_tune_get.restype = C.c_int
         L.grid_trace_enable.argtypes = [C.c_int]
         L.grid_trace_read.argtypes = [C.POINTER(grid_trace_entry), C.c_int, C.POINTER(C.c_int)]
         for name in ("grid_trace_enable", "grid_trace_read", "grid_count", "grid_build", "grid_expand", "grid_count_batched", "grid_build_batched",
@@ -343,3 +349,21 @@ def trace_read() -> dict:
     n = C.c_int(0)
     _check(lib().grid_trace_read(arr, 64, C.byref(n)), "grid_trace_read")
     return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(n.value, 64))}
+
+
+def tune_set(key: str, value: int):
+    _check(lib().grid_tune_set(key.encode(), int(value)), f"grid_tune_set({key})")
+
+
+def tune_get(key: str) -> int:
+    v = C.c_int(0)
+    _check(lib().grid_tune_get(key.encode(), C.byref(v)), f"grid_tune_get({key})")
+    return int(v.value)
+
+
+def sort_plan(nbits: int):
+    """(passes, [digit widths], kernel digit bits) for an nbits-bit key under the current knobs."""
+    p, k = C.c_uint32(0), C.c_uint32(0)
+    w = (C.c_uint32 * 4)()
+    _check(lib().grid_sort_plan(nbits, C.byref(p), w, C.byref(k)), "grid_sort_plan")
+    return int(p.value), [int(w[i]) for i in range(p.value)], int(k.value)

@@ -142,20 +142,33 @@ GB_DEV uint64_t lookback_wave(uint64_t* status, uint32_t tile, uint64_t aggregat
   return excl;
 }
 
-// Serial look-back by one thread along status[(tile - 1) * stride + col], ...
+// Look-back by one thread along status[(tile - 1) * stride + col], ...,
+// reading four predecessors per round so a chain of aggregates costs one
+// memory latency per four tiles.
 GB_DEV uint64_t lookback_thread(uint64_t* status, uint32_t stride, uint32_t col, uint32_t tile) {
+  constexpr int kAhead = 4;
   uint64_t excl = 0;
   int64_t j = static_cast<int64_t>(tile) - 1;
   while (j >= 0) {
-    const uint64_t s = status_load(status + static_cast<uint64_t>(j) * stride + col);
-    const uint64_t flag = s >> 62;
-    if (flag == kFlagInvalid) {
-      __builtin_amdgcn_s_sleep(1);
-      continue;
+    uint64_t s[kAhead];
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u)
+      s[u] = j - u >= 0 ? status_load(status + static_cast<uint64_t>(j - u) * stride + col) : (kFlagPrefix << 62);
+    bool done = false, stalled = false;
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) {
+      if (done || stalled) continue;
+      const uint64_t flag = s[u] >> 62;
+      if (flag == kFlagInvalid) {
+        stalled = true;
+      } else {
+        excl += s[u] & kValueMask;
+        --j;
+        if (flag == kFlagPrefix) done = true;
+      }
     }
-    excl += s & kValueMask;
-    if (flag == kFlagPrefix) break;
-    --j;
+    if (done) break;
+    if (stalled) __builtin_amdgcn_s_sleep(1);
   }
   return excl;
 }

@@ -119,7 +119,11 @@ struct Plan {
   int rb;  // template radix bits (8..11)
 };
 
-int g_max_digit_bits = 9;  // tunable: widest digit a pass may use
+// Tunables (grid_tune_set): the widest digit a radix pass may use, and whether
+// the first radix pass regenerates its keys from the expansion (fused) or the
+// expansion writes the object-order pairs and every pass reads arrays.
+int g_max_digit_bits = 9;
+int g_fused_expand = 0;
 
 Plan make_plan(uint32_t bits, int max_digit = -1) {
   Plan p{};
@@ -129,7 +133,9 @@ Plan make_plan(uint32_t bits, int max_digit = -1) {
     p.rb = 8;
     return p;
   }
-  const uint32_t passes = (bits + md - 1) / md;
+  // at most 4 passes (the plan's arrays and the histogram slots): a narrow
+  // digit limit on a wide key widens the digits instead (32 bits / 4 = 8)
+  const uint32_t passes = std::min<uint32_t>(4, (bits + md - 1) / md);
   const uint32_t w = (bits + passes - 1) / passes;
   p.sp.passes = passes;
   for (uint32_t i = 0; i < passes; ++i) {
@@ -294,18 +300,43 @@ uint32_t persistent_blocks(uint64_t tiles, int per_cu) {
   return static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap)));
 }
 
-template <bool B>
+template <int RB, bool B>
 int launch_expand(Build& b, uint32_t* cells, uint32_t* objs, uint64_t npairs) {
   if (npairs == 0) return GRID_OK;
+  if (!cells || !objs) return GRID_E_INVAL;
   ExpandOutArgs a{};
   a.ex = expand_args(b);
   a.cells = cells;
   a.objs = objs;
+  a.plan = b.plan.sp;
+  a.hist = at<uint32_t>(b.ws, b.L.hist);
+  a.sort_status = at<uint64_t>(b.ws, b.L.sort_status);
+  a.status_stride = static_cast<uint64_t>(b.L.nsort_tiles_cap) * (RB > 0 ? (1u << RB) : 1u);
   a.ctl = at<Control>(b.ws, b.L.ctl);
-  TraceScope ts(b.s, "expand");
-  expand_kernel<kSortBlock, kSortK, B><<<persistent_blocks(ceil_div(npairs, kSortTile), 4), kSortBlock, 0, b.s>>>(a);
+  TraceScope ts(b.s, RB > 0 ? "expand_hist" : "expand");
+  expand_kernel<kSortBlock, kSortK, RB, B><<<persistent_blocks(ceil_div(npairs, kSortTile), 4), kSortBlock, 0, b.s>>>(a);
   GB_LAUNCHED();
   return GRID_OK;
+}
+
+// Destination of writer i of the sort sequence (i = -1: the unfused
+// expansion, i = 0..P-1: the radix passes).  Plain builds end in the caller's
+// arrays; batched builds end in the per-grid outputs (nullptr here).
+struct Dest {
+  uint32_t* k;
+  uint32_t* v;
+};
+Dest sort_dest(const Build& b, bool batched, int i, uint32_t P, uint32_t* out_k, uint32_t* out_v) {
+  uint32_t* ak = at<uint32_t>(b.ws, b.L.keys_alt);
+  uint32_t* av = at<uint32_t>(b.ws, b.L.vals_alt);
+  if (batched) {
+    if (i == static_cast<int>(P) - 1) return {nullptr, nullptr};
+    const bool first = ((i + 1) % 2) == 0;  // -1 -> alt, 0 -> alt2, 1 -> alt, ...
+    if (!g_fused_expand) return first ? Dest{ak, av} : Dest{at<uint32_t>(b.ws, b.L.keys_alt2), at<uint32_t>(b.ws, b.L.vals_alt2)};
+    return (i % 2 == 0) ? Dest{ak, av} : Dest{at<uint32_t>(b.ws, b.L.keys_alt2), at<uint32_t>(b.ws, b.L.vals_alt2)};
+  }
+  const bool to_out = ((static_cast<int>(P) - 1 - i) % 2) == 0;
+  return to_out ? Dest{out_k, out_v} : Dest{ak, av};
 }
 
 template <int RB, bool B>
@@ -313,7 +344,11 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
   const SortPlan& sp = b.plan.sp;
   const uint32_t ntiles = static_cast<uint32_t>(ceil_div(npairs, kSortTile));
   Control* ctl = at<Control>(b.ws, b.L.ctl);
-  {
+  const uint32_t P = sp.passes;
+  const bool fused = g_fused_expand != 0;
+  const uint32_t* in_k = nullptr;
+  const uint32_t* in_v = nullptr;
+  if (fused) {
     HistArgs h{};
     h.ex = expand_args(b);
     h.plan = sp;
@@ -324,33 +359,22 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
     TraceScope ts(b.s, "hist");
     hist_kernel<kSortBlock, kSortK, RB, B><<<persistent_blocks(ntiles, 3), kSortBlock, 0, b.s>>>(h);
     GB_LAUNCHED();
+  } else {
+    const Dest d = sort_dest(b, B, -1, P, out_cells, out_objs);
+    int st = launch_expand<RB, B>(b, d.k, d.v, npairs);
+    if (st) return st;
+    in_k = d.k;
+    in_v = d.v;
   }
-  uint32_t* alt_k = at<uint32_t>(b.ws, b.L.keys_alt);
-  uint32_t* alt_v = at<uint32_t>(b.ws, b.L.vals_alt);
-  uint32_t* alt2_k = at<uint32_t>(b.ws, b.L.keys_alt2);
-  uint32_t* alt2_v = at<uint32_t>(b.ws, b.L.vals_alt2);
-  const uint32_t P = sp.passes;
-  const uint32_t blocks = persistent_blocks(ntiles, 2);
-  const uint32_t* in_k = nullptr;
-  const uint32_t* in_v = nullptr;
   for (uint32_t p = 0; p < P; ++p) {
-    uint32_t* ok;
-    uint32_t* ov;
-    if (B) {
-      // the last pass writes each grid's own outputs; earlier ones alternate
-      ok = p + 1 == P ? nullptr : (p % 2 == 0 ? alt_k : alt2_k);
-      ov = p + 1 == P ? nullptr : (p % 2 == 0 ? alt_v : alt2_v);
-    } else {
-      const bool to_out = ((P - 1 - p) % 2) == 0;
-      ok = to_out ? out_cells : alt_k;
-      ov = to_out ? out_objs : alt_v;
-    }
-    if ((!B || p + 1 < P) && (!ok || !ov)) return GRID_E_INVAL;  // never launch a pass without a destination
+    const Dest d = sort_dest(b, B, static_cast<int>(p), P, out_cells, out_objs);
+    const bool last = p + 1 == P;
+    if ((!B || !last) && (!d.k || !d.v)) return GRID_E_INVAL;  // never launch a pass without a destination
     SortPassArgs a{};
     a.keys_in = in_k;
     a.vals_in = in_v;
-    a.keys_out = ok;
-    a.vals_out = ov;
+    a.keys_out = d.k;
+    a.vals_out = d.v;
     a.ex = expand_args(b);
     a.hist = at<uint32_t>(b.ws, b.L.hist) + p * kRadixMax;
     a.status = at<uint64_t>(b.ws, b.L.sort_status) + static_cast<uint64_t>(p) * b.L.nsort_tiles_cap * (1u << RB);
@@ -361,9 +385,10 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
     a.counter = kCtrSort0 + p;
     a.run = at<GridRun>(b.ws, b.L.run);
     a.ctl = ctl;
-    const bool last = p + 1 == P;
-    TraceScope ts(b.s, p == 0 ? "onesweep_expand" : "onesweep");
-    if (p == 0) {
+    const bool regen = fused && p == 0;
+    TraceScope ts(b.s, regen ? "onesweep_expand" : "onesweep");
+    const uint32_t blocks = persistent_blocks(ntiles, regen ? 1 : 2);
+    if (regen) {
       if (B && last)
         onesweep_kernel<kSortBlock, kSortK, RB, kFromExpansion, kToGrids, B><<<blocks, kSortBlock, 0, b.s>>>(a);
       else
@@ -375,14 +400,22 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
         onesweep_kernel<kSortBlock, kSortK, RB, kFromArrays, kToArrays, B><<<blocks, kSortBlock, 0, b.s>>>(a);
     }
     GB_LAUNCHED();
-    in_k = ok;
-    in_v = ov;
+    in_k = d.k;
+    in_v = d.v;
   }
   return GRID_OK;
 }
 
+bool plan_ok(const Plan& p) {
+  if (p.sp.passes > 4) return false;
+  for (uint32_t i = 0; i < p.sp.passes; ++i)
+    if (p.sp.width[i] < 1 || static_cast<int>(p.sp.width[i]) > p.rb || p.sp.shift[i] + p.sp.width[i] > 32) return false;
+  return p.rb >= 8 && p.rb <= kMaxRadixBits;
+}
+
 template <bool B>
 int launch_sort(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t npairs) {
+  if (!plan_ok(b.plan)) return GRID_E_INVAL;  // never launch digits wider than the kernel's counters
   switch (b.plan.rb) {
     case 8: return launch_sort_rb<8, B>(b, out_cells, out_objs, npairs);
     case 9: return launch_sort_rb<9, B>(b, out_cells, out_objs, npairs);
@@ -521,7 +554,7 @@ int grid_build(const float* verts_soa, uint32_t nverts, const uint32_t* tris, ui
   if (h.npairs > out->cap_pairs) return GRID_E_CAPACITY;
   if ((st = launch_plan<false>(b))) return st;
   if (b.plan.sp.passes == 0) {
-    if ((st = launch_expand<false>(b, out->cells, out->objs, h.npairs))) return st;
+    if ((st = launch_expand<0, false>(b, out->cells, out->objs, h.npairs))) return st;
   } else if (h.npairs > 0) {
     if ((st = launch_sort<false>(b, out->cells, out->objs, h.npairs))) return st;
   }
@@ -541,7 +574,7 @@ int grid_expand(const float* verts_soa, uint32_t nverts, const uint32_t* tris, u
   *npairs = h.npairs;
   if (st) return st;
   if (h.npairs > cap_pairs) return GRID_E_CAPACITY;
-  if ((st = launch_expand<false>(b, cells, objs, h.npairs))) return st;
+  if ((st = launch_expand<0, false>(b, cells, objs, h.npairs))) return st;
   GB_TRY(hipStreamSynchronize(b.s));
   return GRID_OK;
 }
@@ -799,6 +832,7 @@ int grid_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t
   if (n == 0 || nbits == 0) return GRID_OK;
   if (!keys || !vals || !keys_alt || !vals_alt || !ws) return GRID_E_INVAL;
   const Plan plan = make_plan(nbits);
+  if (!plan_ok(plan)) return GRID_E_INVAL;
   const SortLayout L = sort_layout(n, plan);
   if (ws_bytes < L.total) return GRID_E_NOMEM;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -892,6 +926,45 @@ int grid_trace_read(grid_trace_entry* out, int max_entries, int* n_entries) {
   *n_entries = static_cast<int>(agg.size());
   for (int i = 0; i < static_cast<int>(agg.size()) && i < max_entries; ++i) out[i] = agg[i];
   return status;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// Tuning knobs.
+// ---------------------------------------------------------------------------------
+extern "C" {
+
+int grid_tune_set(const char* key, int value) {
+  if (!key) return GRID_E_INVAL;
+  if (std::strcmp(key, "max_digit_bits") == 0) {
+    if (value < 4 || value > kMaxRadixBits) return GRID_E_INVAL;
+    g_max_digit_bits = value;
+    return GRID_OK;
+  }
+  if (std::strcmp(key, "fused_expand") == 0) {
+    if (value != 0 && value != 1) return GRID_E_INVAL;
+    g_fused_expand = value;
+    return GRID_OK;
+  }
+  return GRID_E_INVAL;
+}
+
+int grid_sort_plan(uint32_t nbits, uint32_t* passes, uint32_t widths[4], uint32_t* kernel_digit_bits) {
+  if (nbits > 32 || !passes || !widths || !kernel_digit_bits) return GRID_E_INVAL;
+  const Plan p = make_plan(nbits);
+  if (!plan_ok(p) && nbits > 0) return GRID_E_INVAL;
+  *passes = p.sp.passes;
+  for (int i = 0; i < 4; ++i) widths[i] = i < static_cast<int>(p.sp.passes) ? p.sp.width[i] : 0;
+  *kernel_digit_bits = static_cast<uint32_t>(p.rb);
+  return GRID_OK;
+}
+
+int grid_tune_get(const char* key, int* value) {
+  if (!key || !value) return GRID_E_INVAL;
+  if (std::strcmp(key, "max_digit_bits") == 0) { *value = g_max_digit_bits; return GRID_OK; }
+  if (std::strcmp(key, "fused_expand") == 0) { *value = g_fused_expand; return GRID_OK; }
+  return GRID_E_INVAL;
 }
 
 }  // extern "C"

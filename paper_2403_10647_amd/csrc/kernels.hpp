@@ -84,28 +84,49 @@ __global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
   const uint32_t ntiles = (a.ntris + Tile - 1) / Tile;
   uint32_t g = Batched && base < a.ntris ? grid_search<Batched>(a.gs, static_cast<uint32_t>(base)) : 0;
 
+  // all index loads, then all vertex loads, then the arithmetic
+  uint32_t gi[K], idx[K][3];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint64_t t = base + static_cast<uint64_t>(k) * Block + tid;
+    const uint32_t tc = static_cast<uint32_t>(t < a.ntris ? t : a.ntris - 1);
+    g = grid_of_tri<Batched>(a.gs, tc, g);
+    gi[k] = g;
+    const GridDev& G = grid_at<Batched>(a.gs, g);
+    const uint32_t* tri = G.tris + 3 * static_cast<uint64_t>(tc - G.tri_base);
+    idx[k][0] = tri[0];
+    idx[k][1] = tri[1];
+    idx[k][2] = tri[2];
+  }
+  float p[K][3][3];
+  bool bad[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const GridDev& G = grid_at<Batched>(a.gs, gi[k]);
+    bad[k] = idx[k][0] >= G.nverts || idx[k][1] >= G.nverts || idx[k][2] >= G.nverts;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const float* v = G.verts + static_cast<uint64_t>(ax) * G.nverts;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) p[k][ax][c] = bad[k] ? 0.0f : v[idx[k][c]];  // no load for a bad index
+    }
+  }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const uint64_t t = base + static_cast<uint64_t>(k) * Block + tid;
     uint32_t cnt = 0;
     if (t < a.ntris) {
-      g = grid_of_tri<Batched>(a.gs, static_cast<uint32_t>(t), g);
-      const GridDev& G = grid_at<Batched>(a.gs, g);
-      const uint32_t lt = static_cast<uint32_t>(t) - G.tri_base;
-      const uint32_t* tri = G.tris + 3 * static_cast<uint64_t>(lt);
-      const uint32_t i0 = tri[0], i1 = tri[1], i2 = tri[2];
+      const GridDev& G = grid_at<Batched>(a.gs, gi[k]);
       uint64_t packed = 0;
       cnt = 1;
-      if (i0 >= G.nverts || i1 >= G.nverts || i2 >= G.nverts) {
+      if (bad[k]) {
         atomicOr(&a.ctl->error, kErrBadIndex);
       } else {
         uint32_t lo[3], m[3];
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-          const float* v = G.verts + static_cast<uint64_t>(ax) * G.nverts;
-          const float p0 = v[i0], p1 = v[i1], p2 = v[i2];
-          const float pmin = fminf(fminf(p0, p1), p2);
-          const float pmax = fmaxf(fmaxf(p0, p1), p2);
+          const float pmin = fminf(fminf(p[k][ax][0], p[k][ax][1]), p[k][ax][2]);
+          const float pmax = fmaxf(fmaxf(p[k][ax][0], p[k][ax][1]), p[k][ax][2]);
           const uint32_t cl = cell_coord(pmin, G.lo[ax], G.inv[ax], G.res[ax] - 1);
           const uint32_t ch = cell_coord(pmax, G.lo[ax], G.inv[ax], G.res[ax] - 1);
           lo[ax] = cl;
@@ -181,85 +202,144 @@ struct ExpandArgs {
 };
 
 template <int Block, int K, bool Batched>
-GB_DEV void expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs, uint32_t ntiles, uint32_t* s_owner,
+GB_DEV void expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs, uint32_t ntiles, uint32_t* s_slot,
                         uint32_t* s_wtot, uint32_t (&keys)[K], uint32_t (&vals)[K]) {
   constexpr int N = Block * K;
+  static_assert(N <= 65536, "slot and object offsets are packed in 16 bits");
+  constexpr int kHeadBatch = 4;
   const uint32_t tid = threadIdx.x;
   const uint64_t base = static_cast<uint64_t>(tile) * N;
   const uint32_t n = static_cast<uint32_t>(npairs - base < N ? npairs - base : N);
   const uint32_t t0 = a.tfo[tile];
   const uint32_t thi = tile + 1 < ntiles ? a.tfo[tile + 1] : a.ntris - 1;
+  const uint32_t s0 = a.start[t0];  // the carried-in owner starts at or before the tile
 #pragma unroll
-  for (int k = 0; k < K; ++k) s_owner[k * Block + tid] = 0;
+  for (int k = 0; k < K; ++k) s_slot[k * Block + tid] = 0;
   __syncthreads();
-  if (tid == 0) s_owner[0] = t0;
-  for (uint32_t t = t0 + 1 + tid; t <= thi; t += Block) {
-    const uint64_t s = a.start[t];
-    if (s < base + n) s_owner[s - base] = t;
+  // Each object starting inside the tile marks its first slot with
+  // (object offset from t0) << 16 | slot; both fields grow along the tile, so
+  // a max-scan hands every slot its owner and the owner's first slot.
+  const uint32_t nobj = thi - t0;
+  for (uint32_t j0 = 0; j0 < nobj; j0 += Block * kHeadBatch) {
+    uint32_t st[kHeadBatch];
+#pragma unroll
+    for (int u = 0; u < kHeadBatch; ++u) {
+      const uint32_t j = j0 + u * Block + tid + 1;
+      st[u] = a.start[t0 + (j <= nobj ? j : nobj)];
+    }
+#pragma unroll
+    for (int u = 0; u < kHeadBatch; ++u) {
+      const uint32_t j = j0 + u * Block + tid + 1;
+      const uint32_t slot = st[u] - static_cast<uint32_t>(base);
+      if (j <= nobj && slot < n) s_slot[slot] = (j << 16) | slot;
+    }
   }
   __syncthreads();
-  // inclusive max-scan over the tile's slots, K consecutive slots per thread
   uint32_t run = 0;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const uint32_t v = s_owner[tid * K + k];
+    const uint32_t v = s_slot[tid * K + k];
     run = run > v ? run : v;
   }
-  const uint32_t before = block_exclusive_max<Block>(run, s_wtot);
-  run = before;
+  run = block_exclusive_max<Block>(run, s_wtot);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const uint32_t v = s_owner[tid * K + k];
+    const uint32_t v = s_slot[tid * K + k];
     run = run > v ? run : v;
-    s_owner[tid * K + k] = run;
+    s_slot[tid * K + k] = run;
   }
   __syncthreads();
   const uint32_t lane = lane_id();
   const uint32_t w = tid / kWave;
   uint32_t gcur = 0;
   if constexpr (Batched) gcur = grid_search<true>(a.gs, t0);
+  // items in chunks: all box gathers of a chunk are in flight together, while
+  // the live registers stay bounded
+  constexpr int KC = K >= 8 ? 8 : K;
+  static_assert(K % KC == 0, "items per thread must be a multiple of the chunk");
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const uint32_t idx = w * (kWave * K) + k * kWave + lane;
-    if (idx < n) {
-      const uint32_t t = s_owner[idx];
-      const uint32_t rid = static_cast<uint32_t>(base + idx) - a.start[t];
-      const Box b = unpack_box(a.box[t]);
-      uint32_t g = grid_of_tri<Batched>(a.gs, t, gcur);
+  for (int c0 = 0; c0 < K; c0 += KC) {
+    uint32_t obj[KC], rid[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      const uint32_t idx = w * (kWave * K) + (c0 + c) * kWave + lane;
+      const uint32_t ii = idx < n ? idx : n - 1;
+      const uint32_t v = s_slot[ii];
+      const uint32_t r = v >> 16;
+      obj[c] = t0 + r;
+      rid[c] = r == 0 ? static_cast<uint32_t>(base) + ii - s0 : ii - (v & 0xFFFFu);
+    }
+    uint64_t bx[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) bx[c] = a.box[obj[c]];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      const int k = c0 + c;
+      const uint32_t idx = w * (kWave * K) + k * kWave + lane;
+      const Box b = unpack_box(bx[c]);
+      const uint32_t g = grid_of_tri<Batched>(a.gs, obj[c], gcur);
       const GridDev& G = grid_at<Batched>(a.gs, g);
-      const uint32_t cell = cell_of(b, rid, G.res[0], G.res[0] * G.res[1]);
+      const uint32_t cell = cell_of(b, rid[c], G.res[0], G.res[0] * G.res[1]);
       if constexpr (Batched) {
         keys[k] = (g << a.gs.cell_bits) | cell;
-        vals[k] = t - G.tri_base;
+        vals[k] = obj[c] - G.tri_base;
       } else {
         keys[k] = cell;
-        vals[k] = t;
+        vals[k] = obj[c];
       }
-    } else {
-      keys[k] = 0xFFFFFFFFu;
-      vals[k] = 0;
+      if (idx >= n) {
+        keys[k] = 0xFFFFFFFFu;
+        vals[k] = 0;
+      }
     }
   }
   __syncthreads();
 }
 
-// Object-order pair lists written out (the expansion on its own).
+// ---------------------------------------------------------------------------
+// Radix sort plan: up to 4 passes over the low `bits` bits of the key.
+// ---------------------------------------------------------------------------
+struct SortPlan {
+  uint32_t passes;
+  uint32_t shift[4];
+  uint32_t width[4];
+};
+
+constexpr int kRadixMax = 2048;
+
+// Object-order pair lists written out (the expansion on its own).  With
+// RB > 0 it also accumulates the digit histograms of every radix pass from
+// the keys it holds, and clears the passes' look-back words, so the sort can
+// start from these arrays without another read.
 struct ExpandOutArgs {
   ExpandArgs ex;
   uint32_t* cells;
   uint32_t* objs;
-  uint32_t tile_shift;
+  SortPlan plan;
+  uint32_t* hist;           // [4][kRadixMax]
+  uint64_t* sort_status;    // [passes][status_stride]
+  uint64_t status_stride;
   Control* ctl;
 };
 
-template <int Block, int K, bool Batched>
+template <int Block, int K, int RB, bool Batched>
 __global__ __launch_bounds__(Block) void expand_kernel(ExpandOutArgs a) {
   constexpr int N = Block * K;
+  constexpr int R = RB > 0 ? 1 << RB : 1;
   __shared__ uint32_t s_owner[N];
+  __shared__ uint32_t s_hist[RB > 0 ? 4 * R : 1];
   __shared__ uint32_t s_wtot[Block / kWave];
   __shared__ uint32_t s_tile;
   const uint64_t npairs = a.ctl->npairs;
   const uint32_t ntiles = static_cast<uint32_t>((npairs + N - 1) / N);
+  if constexpr (RB > 0) {
+    const uint64_t per_pass = static_cast<uint64_t>(ntiles) * R;
+    const uint64_t nwords = static_cast<uint64_t>(a.plan.passes) * per_pass;
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * Block + threadIdx.x; i < nwords;
+         i += static_cast<uint64_t>(gridDim.x) * Block)
+      a.sort_status[(i / per_pass) * a.status_stride + i % per_pass] = 0;
+    for (int i = threadIdx.x; i < 4 * R; i += Block) s_hist[i] = 0;
+  }
   while (true) {
     const uint32_t tile = next_tile(&a.ctl->tile_counter[kCtrExpand], &s_tile);
     if (tile >= ntiles) break;
@@ -273,19 +353,21 @@ __global__ __launch_bounds__(Block) void expand_kernel(ExpandOutArgs a) {
       if (i < npairs) {
         a.cells[i] = keys[k];
         a.objs[i] = vals[k];
+        if constexpr (RB > 0) {
+          for (uint32_t p = 0; p < a.plan.passes; ++p)
+            atomicAdd(&s_hist[p * R + ((keys[k] >> a.plan.shift[p]) & ((1u << a.plan.width[p]) - 1u))], 1u);
+        }
       }
     }
   }
+  if constexpr (RB > 0) {
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < a.plan.passes * R; i += Block) {
+      const uint32_t v = s_hist[i];
+      if (v) atomicAdd(&a.hist[(i / R) * kRadixMax + (i % R)], v);
+    }
+  }
 }
-
-// ---------------------------------------------------------------------------
-// Radix sort plan: up to 4 passes over the low `bits` bits of the key.
-// ---------------------------------------------------------------------------
-struct SortPlan {
-  uint32_t passes;
-  uint32_t shift[4];
-  uint32_t width[4];
-};
 
 // One read of the keys (regenerated from the expansion) for the digit
 // histograms of every pass; also clears the look-back words of every pass.
@@ -297,8 +379,6 @@ struct HistArgs {
   uint64_t status_stride;   // words per pass (capacity tiles * radix)
   Control* ctl;
 };
-
-constexpr int kRadixMax = 2048;
 
 template <int Block, int K, int RB, bool Batched>
 __global__ __launch_bounds__(Block) void hist_kernel(HistArgs a) {

@@ -29,8 +29,10 @@ struct SortPassArgs {
   Control* ctl;
 };
 
+// Two workgroups per CU when the keys come from arrays (at most 128 VGPRs);
+// the regenerating variant needs more registers and runs one per CU.
 template <int Block, int K, int RB, int Source, int Sink, bool Batched>
-__global__ __launch_bounds__(Block) void onesweep_kernel(SortPassArgs a) {
+__global__ __launch_bounds__(Block, Source == kFromArrays ? 4 : 2) void onesweep_kernel(SortPassArgs a) {
   constexpr int N = Block * K;
   constexpr int R = 1 << RB;
   constexpr int W = Block / kWave;
@@ -61,16 +63,19 @@ __global__ __launch_bounds__(Block) void onesweep_kernel(SortPassArgs a) {
     if constexpr (Source == kFromExpansion) {
       expand_tile<Block, K, Batched>(a.ex, tile, n, ntiles, s_stage, s_wtot, keys, vals);
     } else {
+      // branch-free loads (the tail re-reads the last element) keep all of
+      // them in flight at once
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const uint32_t idx = w * (kWave * K) + k * kWave + lane;
-        if (idx < nt) {
-          keys[k] = a.keys_in[base + idx];
-          vals[k] = a.vals_in[base + idx];
-        } else {
-          keys[k] = 0xFFFFFFFFu;
-          vals[k] = 0;
-        }
+        const uint64_t src = base + (idx < nt ? idx : nt - 1);
+        keys[k] = a.keys_in[src];
+        vals[k] = a.vals_in[src];
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const uint32_t idx = w * (kWave * K) + k * kWave + lane;
+        if (idx >= nt) keys[k] = 0xFFFFFFFFu;
       }
     }
 
@@ -118,39 +123,13 @@ __global__ __launch_bounds__(Block) void onesweep_kernel(SortPassArgs a) {
       tsum += run;
     }
     uint32_t ttot;
-    uint32_t texcl = block_exclusive_sum<Block>(tsum, s_wtot, ttot);
-    if (tile == 0) {
-      // global digit offsets: exclusive scan of the pass histogram
-      uint32_t hsum = 0, hv[DPT];
+    const uint32_t texcl0 = block_exclusive_sum<Block>(tsum, s_wtot, ttot);
+    {
+      uint32_t texcl = texcl0;
 #pragma unroll
       for (int j = 0; j < DPT; ++j) {
         const uint32_t d = tid * DPT + j;
-        hv[j] = d < static_cast<uint32_t>(R) ? a.hist[d] : 0u;
-        hsum += hv[j];
-      }
-      uint32_t htot;
-      uint32_t hex = block_exclusive_sum<Block>(hsum, s_wtot, htot);
-#pragma unroll
-      for (int j = 0; j < DPT; ++j) {
-        const uint32_t d = tid * DPT + j;
-        if (d < static_cast<uint32_t>(R)) {
-          status_store(a.status + d, kFlagPrefix, static_cast<uint64_t>(hex) + dcount[j]);
-          s_tile_excl[d] = texcl;
-          s_dst[d] = hex - texcl;
-        }
-        hex += hv[j];
-        texcl += dcount[j];
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < DPT; ++j) {
-        const uint32_t d = tid * DPT + j;
-        if (d < static_cast<uint32_t>(R)) {
-          const uint64_t ex = lookback_thread(a.status, R, d, tile);
-          status_store(a.status + static_cast<uint64_t>(tile) * R + d, kFlagPrefix, ex + dcount[j]);
-          s_tile_excl[d] = texcl;
-          s_dst[d] = static_cast<uint32_t>(ex) - texcl;
-        }
+        if (d < static_cast<uint32_t>(R)) s_tile_excl[d] = texcl;
         texcl += dcount[j];
       }
     }
@@ -170,6 +149,42 @@ __global__ __launch_bounds__(Block) void onesweep_kernel(SortPassArgs a) {
       if (idx < nt) {
         s_stage[pos[k]] = keys[k];
         s_stage[N + pos[k]] = vals[k];
+      }
+    }
+
+    // ---- global digit offsets: tile 0 from the histogram, others by look-back ----
+    if (tile == 0) {
+      uint32_t hsum = 0, hv[DPT];
+#pragma unroll
+      for (int j = 0; j < DPT; ++j) {
+        const uint32_t d = tid * DPT + j;
+        hv[j] = d < static_cast<uint32_t>(R) ? a.hist[d] : 0u;
+        hsum += hv[j];
+      }
+      uint32_t htot;
+      uint32_t hex = block_exclusive_sum<Block>(hsum, s_wtot, htot);
+      uint32_t texcl = texcl0;
+#pragma unroll
+      for (int j = 0; j < DPT; ++j) {
+        const uint32_t d = tid * DPT + j;
+        if (d < static_cast<uint32_t>(R)) {
+          status_store(a.status + d, kFlagPrefix, static_cast<uint64_t>(hex) + dcount[j]);
+          s_dst[d] = hex - texcl;
+        }
+        hex += hv[j];
+        texcl += dcount[j];
+      }
+    } else {
+      uint32_t texcl = texcl0;
+#pragma unroll
+      for (int j = 0; j < DPT; ++j) {
+        const uint32_t d = tid * DPT + j;
+        if (d < static_cast<uint32_t>(R)) {
+          const uint64_t ex = lookback_thread(a.status, R, d, tile);
+          status_store(a.status + static_cast<uint64_t>(tile) * R + d, kFlagPrefix, ex + dcount[j]);
+          s_dst[d] = static_cast<uint32_t>(ex) - texcl;
+        }
+        texcl += dcount[j];
       }
     }
     __syncthreads();

@@ -130,3 +130,30 @@ def test_trace_read_without_launches(G):
     G.trace_enable(True)
     assert G.trace_read() == {}
     G.trace_enable(False)
+
+
+@pytest.mark.parametrize("digit", [4, 5, 6, 7, 8, 9, 10, 11])
+def test_sort_plan_is_valid_for_every_width(G, digit):
+    # regression: a narrow digit limit on a wide key once asked for more than
+    # four passes, overflowing the plan and running digits wider than the kernel
+    G.tune_set("max_digit_bits", digit)
+    try:
+        for nbits in range(1, 33):
+            passes, widths, kbits = G.sort_plan(nbits)
+            assert 1 <= passes <= 4
+            assert sum(widths) == nbits
+            assert all(1 <= w <= kbits for w in widths) and 8 <= kbits <= 11
+            assert passes == min(4, -(-nbits // digit))
+        assert G.sort_plan(0)[0] == 0
+    finally:
+        G.tune_set("max_digit_bits", 9)
+
+
+def test_tune_rejects_bad_values(G):
+    with pytest.raises(G.GridError):
+        G.tune_set("max_digit_bits", 3)
+    with pytest.raises(G.GridError):
+        G.tune_set("max_digit_bits", 12)
+    with pytest.raises(G.GridError):
+        G.tune_set("no_such_knob", 1)
+    assert G.tune_get("max_digit_bits") == 9 and G.tune_get("fused_expand") in (0, 1)

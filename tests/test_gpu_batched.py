@@ -124,3 +124,17 @@ def test_batched_chunks_when_keys_exceed_32_bits(G):
         assert torch.equal(p.ranges, res[i].ranges), i
     del res
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("fused,digit", [(0, 8), (1, 8), (1, 10), (0, 11)])
+def test_batched_under_tuning(G, fused, digit):
+    G.tune_set("fused_expand", fused)
+    G.tune_set("max_digit_bits", digit)
+    try:
+        batch = _uneven_batch()[:9]
+        res = G.build_batched([G.GridInput.from_scene(s) for s in batch])
+        for r, s in zip(res, batch):
+            _cmp_oracle(r, s)
+    finally:
+        G.tune_set("fused_expand", 0)
+        G.tune_set("max_digit_bits", 9)

@@ -257,3 +257,18 @@ def test_error_paths(G):
     with pytest.raises(G.GridError) as e:
         G.count(big)
     assert e.value.status == G.GRID_E_OVERFLOW
+
+
+@pytest.mark.parametrize("fused", [0, 1])
+@pytest.mark.parametrize("digit", [4, 8, 9, 10, 11])
+def test_build_under_every_tuning(G, fused, digit):
+    G.tune_set("fused_expand", fused)
+    G.tune_set("max_digit_bits", digit)
+    try:
+        for name, n in [("mixed", 60_000), ("arch", 60_000)]:
+            s = scenes.make_scene(name, ntris=n)
+            s.name = f"{name}-fused{fused}-digit{digit}"
+            _check_build(G, s)
+    finally:
+        G.tune_set("fused_expand", 0)
+        G.tune_set("max_digit_bits", 9)
