@@ -79,15 +79,23 @@ def cpu_baseline(scene, npairs: int) -> dict:
 
 
 def run_copy(steps: int):
+    """A plain device copy of 1 GiB: the counter calibration and the practical HBM ceiling."""
     import torch
     n = 1 << 28  # 1 GiB of float32
     a = torch.ones(n, device="cuda")
     b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(steps):
         b.copy_(a)
+    e1.record()
     torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
     print(json.dumps({"mode": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
-                      "launches": steps}), flush=True)
+                      "launches": steps + 1, "ms_per_copy": round(ms, 4),
+                      "GBps_read_plus_write": round(8 * n / (ms * 1e-3) / 1e9, 1)}), flush=True)
 
 
 def run_batched(G, args) -> dict:

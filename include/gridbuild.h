@@ -166,6 +166,9 @@ int grid_scan_u32(const uint32_t *in, const uint32_t *flags, uint32_t *out, uint
  *                     a b-bit key is sorted in ceil(b / max) passes of equal width
  *   "fused_expand"    1: the first radix pass regenerates its keys from the
  *                     expansion instead of reading them (default 0)
+ *   "sort_shape"      workgroup shape of radix passes that read arrays:
+ *                     0 = 512 threads x 16 pairs, 1 = 256 x 16, 2 = 1024 x 8,
+ *                     3 = 1024 x 16 (default)
  * Outputs never depend on the knobs.  GRID_E_INVAL for an unknown key or value. */
 int grid_tune_set(const char *key, int value);
 int grid_tune_get(const char *key, int *value);

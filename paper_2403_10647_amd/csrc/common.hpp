@@ -142,13 +142,24 @@ GB_DEV uint64_t lookback_wave(uint64_t* status, uint32_t tile, uint64_t aggregat
   return excl;
 }
 
-// Look-back by one thread along status[(tile - 1) * stride + col], ...,
-// reading four predecessors per round so a chain of aggregates costs one
-// memory latency per four tiles.
+// Look-back by one thread along status[(tile - 1) * stride + col], ....
+// The nearest predecessor usually holds its inclusive prefix already, so it
+// is read alone first; a chain of aggregates is then read four tiles per
+// round, one memory latency per four tiles.
 GB_DEV uint64_t lookback_thread(uint64_t* status, uint32_t stride, uint32_t col, uint32_t tile) {
   constexpr int kAhead = 4;
   uint64_t excl = 0;
   int64_t j = static_cast<int64_t>(tile) - 1;
+  if (j < 0) return 0;
+  {
+    const uint64_t s = status_load(status + static_cast<uint64_t>(j) * stride + col);
+    const uint64_t flag = s >> 62;
+    if (flag == kFlagPrefix) return s & kValueMask;
+    if (flag == kFlagAggregate) {
+      excl = s & kValueMask;
+      --j;
+    }
+  }
   while (j >= 0) {
     uint64_t s[kAhead];
 #pragma unroll

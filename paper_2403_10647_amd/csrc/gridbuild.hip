@@ -23,6 +23,7 @@ namespace {
 constexpr int kCountBlock = 256, kCountK = 8;           // 2048 triangles per count tile
 constexpr int kSortBlock = 512, kSortK = 16;            // 8192 pairs per sort tile
 constexpr int kSortTile = kSortBlock * kSortK;
+constexpr int kSortTileMin = 4096;                      // smallest tile of any radix-pass shape
 constexpr int kSortTileShift = 13;
 constexpr int kRangesBlock = 256, kRangesK = 16;        // 4096 merge items per range tile
 constexpr int kMergeTile = kRangesBlock * kRangesK;
@@ -124,6 +125,9 @@ struct Plan {
 // expansion writes the object-order pairs and every pass reads arrays.
 int g_max_digit_bits = 9;
 int g_fused_expand = 0;
+int g_sort_shape = 3;  // radix passes from arrays: 0 = 512 x 16, 1 = 256 x 16, 2 = 1024 x 8, 3 = 1024 x 16
+
+int sort_shape_tile(int shape) { return shape == 1 ? 4096 : shape == 3 ? 16384 : 8192; }
 
 Plan make_plan(uint32_t bits, int max_digit = -1) {
   Plan p{};
@@ -163,7 +167,7 @@ Layout make_layout(uint64_t ntris, uint64_t cap_pairs, uint64_t ncells_plus_grid
     return at;
   };
   L.ncount_tiles = static_cast<uint32_t>(ceil_div(ntris, kCountBlock * kCountK));
-  L.nsort_tiles_cap = static_cast<uint32_t>(ceil_div(cap_pairs, kSortTile));
+  L.nsort_tiles_cap = static_cast<uint32_t>(ceil_div(cap_pairs, kSortTileMin));
   L.ntfo = L.nsort_tiles_cap + 1;
   L.nmerge_tiles_cap = static_cast<uint32_t>(ceil_div(ncells_plus_grids + cap_pairs, kMergeTile) + ngrids);
   L.ctl = take(sizeof(Control));
@@ -300,6 +304,27 @@ uint32_t persistent_blocks(uint64_t tiles, int per_cu) {
   return static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap)));
 }
 
+// Workgroups of `kernel` that fit on the device at once (occupancy query,
+// cached per kernel), so a persistent grid is exactly one resident wave.
+template <class F>
+uint32_t resident_blocks(F kernel, int block, uint64_t tiles) {
+  static std::mutex mu;
+  static std::vector<std::pair<const void*, int>> cache;
+  const void* key = reinterpret_cast<const void*>(kernel);
+  int per_cu = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    for (auto& e : cache)
+      if (e.first == key) per_cu = e.second;
+    if (per_cu == 0) {
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu <= 0)
+        per_cu = 1;
+      cache.emplace_back(key, per_cu);
+    }
+  }
+  return persistent_blocks(tiles, per_cu);
+}
+
 template <int RB, bool B>
 int launch_expand(Build& b, uint32_t* cells, uint32_t* objs, uint64_t npairs) {
   if (npairs == 0) return GRID_OK;
@@ -312,11 +337,60 @@ int launch_expand(Build& b, uint32_t* cells, uint32_t* objs, uint64_t npairs) {
   a.hist = at<uint32_t>(b.ws, b.L.hist);
   a.sort_status = at<uint64_t>(b.ws, b.L.sort_status);
   a.status_stride = static_cast<uint64_t>(b.L.nsort_tiles_cap) * (RB > 0 ? (1u << RB) : 1u);
+  a.clear_tile = kSortTileMin;
   a.ctl = at<Control>(b.ws, b.L.ctl);
   TraceScope ts(b.s, RB > 0 ? "expand_hist" : "expand");
-  expand_kernel<kSortBlock, kSortK, RB, B><<<persistent_blocks(ceil_div(npairs, kSortTile), 4), kSortBlock, 0, b.s>>>(a);
+  auto kern = expand_kernel<kSortBlock, kSortK, RB, B>;
+  kern<<<resident_blocks(kern, kSortBlock, ceil_div(npairs, kSortTile)), kSortBlock, 0, b.s>>>(a);
   GB_LAUNCHED();
   return GRID_OK;
+}
+
+// Each pass runs the kernel built for its own digit width (8..11 bits), so an
+// 8-bit pass of a 25-bit key does not pay for 9-bit ranking.
+int pass_bits(uint32_t width) { return std::max(8, static_cast<int>(width)); }
+
+template <int RB, bool B>
+int launch_pass_rb(const SortPassArgs& a, bool regen, bool to_grids, uint32_t ntiles, hipStream_t s) {
+  if (regen) {
+    if (to_grids) {
+      auto k = onesweep_kernel<kSortBlock, kSortK, RB, kFromExpansion, kToGrids, B>;
+      k<<<resident_blocks(k, kSortBlock, ntiles), kSortBlock, 0, s>>>(a);
+    } else {
+      auto k = onesweep_kernel<kSortBlock, kSortK, RB, kFromExpansion, kToArrays, B>;
+      k<<<resident_blocks(k, kSortBlock, ntiles), kSortBlock, 0, s>>>(a);
+    }
+  } else {
+    if (to_grids) {
+      auto k = onesweep_kernel<kSortBlock, kSortK, RB, kFromArrays, kToGrids, B>;
+      k<<<resident_blocks(k, kSortBlock, ntiles), kSortBlock, 0, s>>>(a);
+    } else if (g_sort_shape == 1) {
+      auto k = onesweep_kernel<256, 16, RB, kFromArrays, kToArrays, B>;
+      k<<<resident_blocks(k, 256, ntiles), 256, 0, s>>>(a);
+    } else if (g_sort_shape == 2) {
+      auto k = onesweep_kernel<1024, 8, RB, kFromArrays, kToArrays, B>;
+      k<<<resident_blocks(k, 1024, ntiles), 1024, 0, s>>>(a);
+    } else if (g_sort_shape == 3) {
+      auto k = onesweep_kernel<1024, 16, RB, kFromArrays, kToArrays, B>;
+      k<<<resident_blocks(k, 1024, ntiles), 1024, 0, s>>>(a);
+    } else {
+      auto k = onesweep_kernel<kSortBlock, kSortK, RB, kFromArrays, kToArrays, B>;
+      k<<<resident_blocks(k, kSortBlock, ntiles), kSortBlock, 0, s>>>(a);
+    }
+  }
+  GB_LAUNCHED();
+  return GRID_OK;
+}
+
+template <bool B>
+int launch_pass(SortPassArgs a, int rb, bool regen, bool to_grids, uint32_t ntiles, hipStream_t s) {
+  switch (rb) {
+    case 8: return launch_pass_rb<8, B>(a, regen, to_grids, ntiles, s);
+    case 9: return launch_pass_rb<9, B>(a, regen, to_grids, ntiles, s);
+    case 10: return launch_pass_rb<10, B>(a, regen, to_grids, ntiles, s);
+    case 11: return launch_pass_rb<11, B>(a, regen, to_grids, ntiles, s);
+    default: return GRID_E_INVAL;
+  }
 }
 
 // Destination of writer i of the sort sequence (i = -1: the unfused
@@ -355,9 +429,11 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
     h.hist = at<uint32_t>(b.ws, b.L.hist);
     h.sort_status = at<uint64_t>(b.ws, b.L.sort_status);
     h.status_stride = static_cast<uint64_t>(b.L.nsort_tiles_cap) * (1u << RB);
+    h.clear_tile = kSortTileMin;
     h.ctl = ctl;
     TraceScope ts(b.s, "hist");
-    hist_kernel<kSortBlock, kSortK, RB, B><<<persistent_blocks(ntiles, 3), kSortBlock, 0, b.s>>>(h);
+    auto kern = hist_kernel<kSortBlock, kSortK, RB, B>;
+    kern<<<resident_blocks(kern, kSortBlock, ntiles), kSortBlock, 0, b.s>>>(h);
     GB_LAUNCHED();
   } else {
     const Dest d = sort_dest(b, B, -1, P, out_cells, out_objs);
@@ -379,26 +455,19 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
     a.hist = at<uint32_t>(b.ws, b.L.hist) + p * kRadixMax;
     a.status = at<uint64_t>(b.ws, b.L.sort_status) + static_cast<uint64_t>(p) * b.L.nsort_tiles_cap * (1u << RB);
     a.n = npairs;
-    a.n_from_ctl = 1;
+    a.n_from_ctl = 1;  // the pass reads NO from the control block
     a.shift = sp.shift[p];
     a.width = sp.width[p];
     a.counter = kCtrSort0 + p;
     a.run = at<GridRun>(b.ws, b.L.run);
     a.ctl = ctl;
     const bool regen = fused && p == 0;
+    const bool shaped = !regen && !(B && last);
+    const uint32_t pass_tiles =
+        static_cast<uint32_t>(ceil_div(npairs, shaped ? sort_shape_tile(g_sort_shape) : kSortTile));
     TraceScope ts(b.s, regen ? "onesweep_expand" : "onesweep");
-    const uint32_t blocks = persistent_blocks(ntiles, regen ? 1 : 2);
-    if (regen) {
-      if (B && last)
-        onesweep_kernel<kSortBlock, kSortK, RB, kFromExpansion, kToGrids, B><<<blocks, kSortBlock, 0, b.s>>>(a);
-      else
-        onesweep_kernel<kSortBlock, kSortK, RB, kFromExpansion, kToArrays, B><<<blocks, kSortBlock, 0, b.s>>>(a);
-    } else {
-      if (B && last)
-        onesweep_kernel<kSortBlock, kSortK, RB, kFromArrays, kToGrids, B><<<blocks, kSortBlock, 0, b.s>>>(a);
-      else
-        onesweep_kernel<kSortBlock, kSortK, RB, kFromArrays, kToArrays, B><<<blocks, kSortBlock, 0, b.s>>>(a);
-    }
+    int st = launch_pass<B>(a, pass_bits(sp.width[p]), regen, B && last, pass_tiles, b.s);
+    if (st) return st;
     GB_LAUNCHED();
     in_k = d.k;
     in_v = d.v;
@@ -947,6 +1016,11 @@ int grid_tune_set(const char* key, int value) {
     g_fused_expand = value;
     return GRID_OK;
   }
+  if (std::strcmp(key, "sort_shape") == 0) {
+    if (value < 0 || value > 3) return GRID_E_INVAL;
+    g_sort_shape = value;
+    return GRID_OK;
+  }
   return GRID_E_INVAL;
 }
 
@@ -964,6 +1038,7 @@ int grid_tune_get(const char* key, int* value) {
   if (!key || !value) return GRID_E_INVAL;
   if (std::strcmp(key, "max_digit_bits") == 0) { *value = g_max_digit_bits; return GRID_OK; }
   if (std::strcmp(key, "fused_expand") == 0) { *value = g_fused_expand; return GRID_OK; }
+  if (std::strcmp(key, "sort_shape") == 0) { *value = g_sort_shape; return GRID_OK; }
   return GRID_E_INVAL;
 }
 

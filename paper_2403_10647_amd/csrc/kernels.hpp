@@ -319,6 +319,7 @@ struct ExpandOutArgs {
   uint32_t* hist;           // [4][kRadixMax]
   uint64_t* sort_status;    // [passes][status_stride]
   uint64_t status_stride;
+  uint32_t clear_tile;      // smallest radix-pass tile: bounds the look-back words to clear
   Control* ctl;
 };
 
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(Block) void expand_kernel(ExpandOutArgs a) {
   const uint64_t npairs = a.ctl->npairs;
   const uint32_t ntiles = static_cast<uint32_t>((npairs + N - 1) / N);
   if constexpr (RB > 0) {
-    const uint64_t per_pass = static_cast<uint64_t>(ntiles) * R;
+    const uint64_t per_pass = ((npairs + a.clear_tile - 1) / a.clear_tile) * R;
     const uint64_t nwords = static_cast<uint64_t>(a.plan.passes) * per_pass;
     for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * Block + threadIdx.x; i < nwords;
          i += static_cast<uint64_t>(gridDim.x) * Block)
@@ -377,6 +378,7 @@ struct HistArgs {
   uint32_t* hist;           // [4][kRadixMax]
   uint64_t* sort_status;    // [passes][status_stride]
   uint64_t status_stride;   // words per pass (capacity tiles * radix)
+  uint32_t clear_tile;      // smallest radix-pass tile: bounds the look-back words to clear
   Control* ctl;
 };
 
@@ -392,7 +394,7 @@ __global__ __launch_bounds__(Block) void hist_kernel(HistArgs a) {
   const uint32_t ntiles = static_cast<uint32_t>((npairs + N - 1) / N);
   // clear the sort passes' look-back words
   {
-    const uint64_t per_pass = static_cast<uint64_t>(ntiles) * R;
+    const uint64_t per_pass = ((npairs + a.clear_tile - 1) / a.clear_tile) * R;
     const uint64_t nwords = static_cast<uint64_t>(a.plan.passes) * per_pass;
     for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * Block + threadIdx.x; i < nwords;
          i += static_cast<uint64_t>(gridDim.x) * Block)

@@ -117,13 +117,11 @@ __global__ __launch_bounds__(Block) void ranges_kernel(RangesArgs a) {
   constexpr int D = Block * K;
   __shared__ uint32_t s_cells[D];
   __shared__ uint32_t s_begin[D];
-  __shared__ uint32_t s_tile;
   const uint32_t G = a.gs.ngrids;
   const uint32_t total = a.run[G].mtile_base;
   const uint32_t tid = threadIdx.x;
-  while (true) {
-    const uint32_t b = next_tile(&a.ctl->tile_counter[kCtrRanges], &s_tile);
-    if (b >= total) break;
+  // tiles are independent: a static stride over them, no tile counter
+  for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
     const uint32_t g = Batched ? grid_of_mtile(a.run, G, b) : 0;
     const GridDev& gd = grid_at<Batched>(a.gs, g);
     const GridRun& gr = a.run[g];
@@ -136,7 +134,18 @@ __global__ __launch_bounds__(Block) void ranges_kernel(RangesArgs a) {
     const uint64_t j1 = lb + 1 < gr.mtiles ? a.splits[b + 1] : gr.npairs;
     const uint64_t i0 = d0 - j0, i1 = d1 - j1;
     const uint32_t np = static_cast<uint32_t>(j1 - j0), ne = static_cast<uint32_t>(i1 - i0);
-    for (uint32_t p = tid; p < np; p += Block) s_cells[p] = gd.out_cells[j0 + p];
+    // all K loads of a thread in flight at once (np <= D = Block * K)
+    uint32_t cv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t p = k * Block + tid;
+      cv[k] = p < np ? gd.out_cells[j0 + p] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t p = k * Block + tid;
+      if (p < np) s_cells[p] = cv[k];
+    }
     __syncthreads();
     // this thread's stretch of the tile's diagonal
     const uint32_t dd0 = tid * K;
@@ -163,7 +172,12 @@ __global__ __launch_bounds__(Block) void ranges_kernel(RangesArgs a) {
     const uint64_t q0 = i0 > 0 ? 2 * i0 - 1 : 0;
     const uint64_t q1e = 2 * i1 - 1;
     const uint64_t q1 = q1e < 2 * ncell ? q1e : 2 * ncell;
-    for (uint64_t q = q0 + tid; q < q1; q += Block) gd.out_ranges[q] = s_begin[(q + 1) / 2 - i0];
+    // at most 2 * D table entries per tile
+#pragma unroll
+    for (int k = 0; k < 2 * K; ++k) {
+      const uint64_t q = q0 + static_cast<uint64_t>(k) * Block + tid;
+      if (q < q1) gd.out_ranges[q] = s_begin[(q + 1) / 2 - i0];
+    }
     __syncthreads();
   }
 }

@@ -37,10 +37,10 @@ __global__ __launch_bounds__(Block, Source == kFromArrays ? 4 : 2) void onesweep
   constexpr int R = 1 << RB;
   constexpr int W = Block / kWave;
   constexpr int DPT = R > Block ? R / Block : 1;        // digits per thread
-  static_assert(W * R * 4 <= N * 8, "wave counters must fit in the staging buffer");
   // staging (keys then values) doubles as the per-wave digit counters and the
   // expansion's owner slots
-  __shared__ uint32_t s_stage[2 * N];
+  constexpr int kStage = 2 * N > W * R ? 2 * N : W * R;
+  __shared__ uint32_t s_stage[kStage];
   __shared__ uint32_t s_tile_excl[R];
   __shared__ uint32_t s_dst[R];
   __shared__ uint32_t s_wtot[W];

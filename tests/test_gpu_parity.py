@@ -272,3 +272,21 @@ def test_build_under_every_tuning(G, fused, digit):
     finally:
         G.tune_set("fused_expand", 0)
         G.tune_set("max_digit_bits", 9)
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+def test_build_under_every_sort_shape(G, shape):
+    G.tune_set("sort_shape", shape)
+    try:
+        for name, n in [("mixed", 100_003), ("arch", 100_003)]:
+            s = scenes.make_scene(name, ntris=n)
+            s.name = f"{name}-shape{shape}"
+            _check_build(G, s)
+        for digit in (8, 11):
+            G.tune_set("max_digit_bits", digit)
+            s = scenes.make_scene("arch", ntris=50_000)
+            s.name = f"arch-shape{shape}-digit{digit}"
+            _check_build(G, s)
+    finally:
+        G.tune_set("sort_shape", 3)
+        G.tune_set("max_digit_bits", 9)
