@@ -38,6 +38,11 @@ GB_DEV uint32_t mbcnt(uint64_t m) {
 
 GB_DEV uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// LDS index with one padding word per 32, so blocked accesses (each thread a
+// run of K consecutive words, K a power of two) spread over all 32 banks.
+GB_DEV uint32_t pad32(uint32_t i) { return i + (i >> 5); }
+constexpr int padded(int n) { return n + n / 32; }
+
 template <int Ctrl, int RowMask = 0xf, int BankMask = 0xf>
 GB_DEV uint32_t dpp(uint32_t old, uint32_t v) {
   return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(static_cast<int>(old), static_cast<int>(v), Ctrl,

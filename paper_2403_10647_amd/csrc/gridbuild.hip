@@ -338,6 +338,7 @@ int launch_expand(Build& b, uint32_t* cells, uint32_t* objs, uint64_t npairs) {
   a.sort_status = at<uint64_t>(b.ws, b.L.sort_status);
   a.status_stride = static_cast<uint64_t>(b.L.nsort_tiles_cap) * (RB > 0 ? (1u << RB) : 1u);
   a.clear_tile = kSortTileMin;
+  a.vec16 = ((reinterpret_cast<uintptr_t>(cells) | reinterpret_cast<uintptr_t>(objs)) & 15u) == 0;
   a.ctl = at<Control>(b.ws, b.L.ctl);
   TraceScope ts(b.s, RB > 0 ? "expand_hist" : "expand");
   auto kern = expand_kernel<kSortBlock, kSortK, RB, B>;

@@ -74,7 +74,7 @@ struct CountArgs {
 template <int Block, int K, bool Batched>
 __global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
   constexpr int Tile = Block * K;
-  __shared__ uint32_t s_val[Tile];
+  __shared__ uint32_t s_val[padded(Tile)];
   __shared__ uint64_t s_wtot[Block / kWave];
   __shared__ uint64_t s_prefix;
   __shared__ uint32_t s_tile;
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
       }
       a.box[t] = packed;
     }
-    s_val[k * Block + tid] = cnt;
+    s_val[pad32(k * Block + tid)] = cnt;
   }
   __syncthreads();
 
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
   uint64_t sum = 0;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    mine[k] = s_val[tid * K + k];
+    mine[k] = s_val[pad32(tid * K + k)];
     sum += mine[k];
   }
   uint64_t total;
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const uint64_t t = base + static_cast<uint64_t>(tid) * K + k;
-    s_val[tid * K + k] = static_cast<uint32_t>(excl);
+    s_val[pad32(tid * K + k)] = static_cast<uint32_t>(excl);
     if (mine[k] != 0 && t < a.ntris) {
       // sort tiles whose first pair this object owns
       uint64_t j = (excl + tmask) >> a.sort_tile_shift;
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const uint64_t t = base + static_cast<uint64_t>(k) * Block + tid;
-    if (t < a.ntris) a.start[t] = s_val[k * Block + tid];
+    if (t < a.ntris) a.start[t] = s_val[pad32(k * Block + tid)];
   }
 }
 
@@ -201,9 +201,21 @@ struct ExpandArgs {
   uint32_t ntris;           // total triangles
 };
 
-template <int Block, int K, bool Batched>
-GB_DEV void expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs, uint32_t ntiles, uint32_t* s_slot,
-                        uint32_t* s_wtot, uint32_t (&keys)[K], uint32_t (&vals)[K]) {
+// Layout of the items a thread holds after expand_tile: wave-striped (item k
+// of lane l in wave w is slot w * 64 * K + k * 64 + l; what the radix rank
+// needs) or blocked (item k of thread t is slot t * K + k; contiguous stores).
+enum ItemLayout : int { kStriped = 0, kBlocked = 1 };
+
+template <int Block, int K, int Layout>
+GB_DEV uint32_t item_slot(uint32_t tid, int k) {
+  if constexpr (Layout == kBlocked) return tid * K + k;
+  else return (tid / kWave) * (kWave * K) + k * kWave + (tid % kWave);
+}
+
+// s_slot must hold padded(Block * K) words.  Returns the tile's item count.
+template <int Block, int K, bool Batched, int Layout = kStriped>
+GB_DEV uint32_t expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs, uint32_t ntiles, uint32_t* s_slot,
+                            uint32_t* s_wtot, uint32_t (&keys)[K], uint32_t (&vals)[K]) {
   constexpr int N = Block * K;
   static_assert(N <= 65536, "slot and object offsets are packed in 16 bits");
   constexpr int kHeadBatch = 4;
@@ -214,7 +226,7 @@ GB_DEV void expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs, uin
   const uint32_t thi = tile + 1 < ntiles ? a.tfo[tile + 1] : a.ntris - 1;
   const uint32_t s0 = a.start[t0];  // the carried-in owner starts at or before the tile
 #pragma unroll
-  for (int k = 0; k < K; ++k) s_slot[k * Block + tid] = 0;
+  for (int k = 0; k < K; ++k) s_slot[pad32(k * Block + tid)] = 0;
   __syncthreads();
   // Each object starting inside the tile marks its first slot with
   // (object offset from t0) << 16 | slot; both fields grow along the tile, so
@@ -231,26 +243,29 @@ GB_DEV void expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs, uin
     for (int u = 0; u < kHeadBatch; ++u) {
       const uint32_t j = j0 + u * Block + tid + 1;
       const uint32_t slot = st[u] - static_cast<uint32_t>(base);
-      if (j <= nobj && slot < n) s_slot[slot] = (j << 16) | slot;
+      if (j <= nobj && slot < n) s_slot[pad32(slot)] = (j << 16) | slot;
     }
   }
   __syncthreads();
+  // inclusive max-scan over the tile's slots, K consecutive slots per thread
+  uint32_t sv[K];
   uint32_t run = 0;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const uint32_t v = s_slot[tid * K + k];
-    run = run > v ? run : v;
+    sv[k] = s_slot[pad32(tid * K + k)];
+    run = run > sv[k] ? run : sv[k];
   }
   run = block_exclusive_max<Block>(run, s_wtot);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const uint32_t v = s_slot[tid * K + k];
-    run = run > v ? run : v;
-    s_slot[tid * K + k] = run;
+    run = run > sv[k] ? run : sv[k];
+    sv[k] = run;
   }
-  __syncthreads();
-  const uint32_t lane = lane_id();
-  const uint32_t w = tid / kWave;
+  if constexpr (Layout == kStriped) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) s_slot[pad32(tid * K + k)] = sv[k];
+    __syncthreads();
+  }
   uint32_t gcur = 0;
   if constexpr (Batched) gcur = grid_search<true>(a.gs, t0);
   // items in chunks: all box gathers of a chunk are in flight together, while
@@ -262,9 +277,9 @@ GB_DEV void expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs, uin
     uint32_t obj[KC], rid[KC];
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
-      const uint32_t idx = w * (kWave * K) + (c0 + c) * kWave + lane;
+      const uint32_t idx = item_slot<Block, K, Layout>(tid, c0 + c);
       const uint32_t ii = idx < n ? idx : n - 1;
-      const uint32_t v = s_slot[ii];
+      const uint32_t v = Layout == kBlocked ? sv[c0 + c] : s_slot[pad32(ii)];
       const uint32_t r = v >> 16;
       obj[c] = t0 + r;
       rid[c] = r == 0 ? static_cast<uint32_t>(base) + ii - s0 : ii - (v & 0xFFFFu);
@@ -275,7 +290,7 @@ GB_DEV void expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs, uin
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
       const int k = c0 + c;
-      const uint32_t idx = w * (kWave * K) + k * kWave + lane;
+      const uint32_t idx = item_slot<Block, K, Layout>(tid, k);
       const Box b = unpack_box(bx[c]);
       const uint32_t g = grid_of_tri<Batched>(a.gs, obj[c], gcur);
       const GridDev& G = grid_at<Batched>(a.gs, g);
@@ -294,6 +309,7 @@ GB_DEV void expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs, uin
     }
   }
   __syncthreads();
+  return n;
 }
 
 // ---------------------------------------------------------------------------
@@ -320,6 +336,7 @@ struct ExpandOutArgs {
   uint64_t* sort_status;    // [passes][status_stride]
   uint64_t status_stride;
   uint32_t clear_tile;      // smallest radix-pass tile: bounds the look-back words to clear
+  uint32_t vec16;           // cells and objs are 16-byte aligned
   Control* ctl;
 };
 
@@ -327,7 +344,8 @@ template <int Block, int K, int RB, bool Batched>
 __global__ __launch_bounds__(Block) void expand_kernel(ExpandOutArgs a) {
   constexpr int N = Block * K;
   constexpr int R = RB > 0 ? 1 << RB : 1;
-  __shared__ uint32_t s_owner[N];
+  static_assert(K % 4 == 0, "items are stored four at a time");
+  __shared__ uint32_t s_owner[padded(N)];
   __shared__ uint32_t s_hist[RB > 0 ? 4 * R : 1];
   __shared__ uint32_t s_wtot[Block / kWave];
   __shared__ uint32_t s_tile;
@@ -345,19 +363,47 @@ __global__ __launch_bounds__(Block) void expand_kernel(ExpandOutArgs a) {
     const uint32_t tile = next_tile(&a.ctl->tile_counter[kCtrExpand], &s_tile);
     if (tile >= ntiles) break;
     uint32_t keys[K], vals[K];
-    expand_tile<Block, K, Batched>(a.ex, tile, npairs, ntiles, s_owner, s_wtot, keys, vals);
+    const uint32_t n = expand_tile<Block, K, Batched, kBlocked>(a.ex, tile, npairs, ntiles, s_owner, s_wtot, keys, vals);
     const uint64_t base = static_cast<uint64_t>(tile) * N;
-    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    const uint32_t first = threadIdx.x * K;
+    // this thread's K consecutive pairs: 16-byte stores when all are present
+    if (a.vec16 && first + K <= n) {
+      uint4* ck = reinterpret_cast<uint4*>(a.cells + base + first);
+      uint4* ov = reinterpret_cast<uint4*>(a.objs + base + first);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const uint64_t i = base + w * (kWave * K) + k * kWave + lane;
-      if (i < npairs) {
-        a.cells[i] = keys[k];
-        a.objs[i] = vals[k];
-        if constexpr (RB > 0) {
-          for (uint32_t p = 0; p < a.plan.passes; ++p)
-            atomicAdd(&s_hist[p * R + ((keys[k] >> a.plan.shift[p]) & ((1u << a.plan.width[p]) - 1u))], 1u);
+      for (int q = 0; q < K / 4; ++q) {
+        ck[q] = make_uint4(keys[4 * q], keys[4 * q + 1], keys[4 * q + 2], keys[4 * q + 3]);
+        ov[q] = make_uint4(vals[4 * q], vals[4 * q + 1], vals[4 * q + 2], vals[4 * q + 3]);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (first + k < n) {
+          a.cells[base + first + k] = keys[k];
+          a.objs[base + first + k] = vals[k];
         }
+      }
+    }
+    if constexpr (RB > 0) {
+      // digit histograms: consecutive pairs of one object mostly share their
+      // upper digits, so each run of equal digits is added once
+      const uint32_t m = first < n ? (n - first < K ? n - first : K) : 0;
+      for (uint32_t p = 0; p < a.plan.passes; ++p) {
+        const uint32_t sh = a.plan.shift[p], dm = (1u << a.plan.width[p]) - 1u;
+        uint32_t cur = 0, cnt = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          if (static_cast<uint32_t>(k) < m) {
+            const uint32_t d = (keys[k] >> sh) & dm;
+            if (cnt != 0 && d != cur) {
+              atomicAdd(&s_hist[p * R + cur], cnt);
+              cnt = 0;
+            }
+            cur = d;
+            ++cnt;
+          }
+        }
+        if (cnt != 0) atomicAdd(&s_hist[p * R + cur], cnt);
       }
     }
   }
@@ -386,7 +432,7 @@ template <int Block, int K, int RB, bool Batched>
 __global__ __launch_bounds__(Block) void hist_kernel(HistArgs a) {
   constexpr int N = Block * K;
   constexpr int R = 1 << RB;
-  __shared__ uint32_t s_owner[N];
+  __shared__ uint32_t s_owner[padded(N)];
   __shared__ uint32_t s_hist[4 * R];
   __shared__ uint32_t s_wtot[Block / kWave];
   __shared__ uint32_t s_tile;

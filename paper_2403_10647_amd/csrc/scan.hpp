@@ -53,8 +53,8 @@ template <int Block, int K, class Op, int Mode>
 __global__ __launch_bounds__(Block) void scan_kernel(ScanArgs a) {
   constexpr int N = Block * K;
   constexpr int W = Block / kWave;
-  __shared__ uint32_t s_v[N];
-  __shared__ uint32_t s_f[Mode == 2 ? N : 1];
+  __shared__ uint32_t s_v[padded(N)];
+  __shared__ uint32_t s_f[Mode == 2 ? padded(N) : 1];
   __shared__ uint64_t s_wave[W];
   __shared__ uint64_t s_prefix;
   __shared__ uint32_t s_tile;
@@ -65,15 +65,15 @@ __global__ __launch_bounds__(Block) void scan_kernel(ScanArgs a) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const uint64_t i = base + k * Block + tid;
-    s_v[k * Block + tid] = i < a.n ? a.in[i] : 0u;
-    if constexpr (Mode == 2) s_f[k * Block + tid] = i < a.n ? a.flags[i] : 0u;
+    s_v[pad32(k * Block + tid)] = i < a.n ? a.in[i] : 0u;
+    if constexpr (Mode == 2) s_f[pad32(k * Block + tid)] = i < a.n ? a.flags[i] : 0u;
   }
   __syncthreads();
   uint64_t agg = Mode == 1 ? 0 : 0;
   uint64_t elem[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    elem[k] = Op::lift(s_v[tid * K + k], Mode == 2 ? s_f[Mode == 2 ? tid * K + k : 0] : 0u);
+    elem[k] = Op::lift(s_v[pad32(tid * K + k)], Mode == 2 ? s_f[Mode == 2 ? pad32(tid * K + k) : 0] : 0u);
     agg = k == 0 ? elem[k] : Op::op(agg, elem[k]);
   }
   // block scan of the per-thread aggregates, in thread order
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(Block) void scan_kernel(ScanArgs a) {
     if constexpr (Mode == 0) o = static_cast<uint32_t>(inc - elem[k]);
     else if constexpr (Mode == 1) o = static_cast<uint32_t>(inc);
     else o = static_cast<uint32_t>((inc & ScanSeg::kSum) - (elem[k] & ScanSeg::kSum));
-    s_v[tid * K + k] = o;
+    s_v[pad32(tid * K + k)] = o;
     run = inc;
     hrun = true;
   }
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(Block) void scan_kernel(ScanArgs a) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const uint64_t i = base + k * Block + tid;
-    if (i < a.n) a.out[i] = s_v[k * Block + tid];
+    if (i < a.n) a.out[i] = s_v[pad32(k * Block + tid)];
   }
 }
 

@@ -39,7 +39,8 @@ __global__ __launch_bounds__(Block, Source == kFromArrays ? 4 : 2) void onesweep
   constexpr int DPT = R > Block ? R / Block : 1;        // digits per thread
   // staging (keys then values) doubles as the per-wave digit counters and the
   // expansion's owner slots
-  constexpr int kStage = 2 * N > W * R ? 2 * N : W * R;
+  constexpr int kStage0 = 2 * N > W * R ? 2 * N : W * R;
+  constexpr int kStage = kStage0 > padded(N) ? kStage0 : padded(N);  // also the expansion's padded slots
   __shared__ uint32_t s_stage[kStage];
   __shared__ uint32_t s_tile_excl[R];
   __shared__ uint32_t s_dst[R];
