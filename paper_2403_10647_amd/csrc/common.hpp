@@ -95,16 +95,27 @@ GB_DEV uint64_t wave_sum64(uint64_t v) {
 }
 
 // Lanes of the wave whose digit equals this lane's (and that are valid).
+// Per bit: a signed one-bit extract gives 0 or all ones, its ballot gives the
+// lanes with the bit set, and each lane collects the lanes that disagree with
+// it, n |= ballot ^ bit (a three-input bitwise op per 32-lane half); the
+// match is the valid lanes outside n.
 template <int Bits>
 GB_DEV uint64_t match_digit(uint32_t d, bool valid) {
-  uint64_t m = ballot(valid);
+  const uint64_t vm = ballot(valid);
+  // lanes that differ from this one in some bit: n |= ballot ^ bit
+  uint32_t nlo = 0, nhi = 0;
 #pragma unroll
   for (int b = 0; b < Bits; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t bb = ballot(bit);
-    m &= bit ? bb : ~bb;
+    // the bit as 0 / all ones, and the wave's lanes that have it set
+    uint32_t bit;
+    uint64_t bb;
+    asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(bit) : "v"(d), "i"(b));
+    asm("v_cmp_ne_u32 %0, 0, %1" : "=s"(bb) : "v"(bit));
+    // n |= ballot ^ bit: table 0xF6 over (n, ballot, bit), index n * 4 + ballot * 2 + bit
+    asm("v_bitop3_b32 %0, %0, %1, %2 bitop3:0xf6" : "+v"(nlo) : "s"(static_cast<uint32_t>(bb)), "v"(bit));
+    asm("v_bitop3_b32 %0, %0, %1, %2 bitop3:0xf6" : "+v"(nhi) : "s"(static_cast<uint32_t>(bb >> 32)), "v"(bit));
   }
-  return m;
+  return vm & ~((static_cast<uint64_t>(nhi) << 32) | nlo);
 }
 
 GB_DEV void status_store(uint64_t* p, uint64_t flag, uint64_t value) {

@@ -1,6 +1,6 @@
 // Host side of the gfx950 grid builder: argument checks, workspace layout,
 // the radix-sort plan and the launch sequence behind the C ABI of gridbuild.h.
-#include "../../include/gridbuild.h"
+#include "gridbuild.h"
 
 #include <hip/hip_runtime.h>
 
