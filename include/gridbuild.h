@@ -168,7 +168,7 @@ int grid_scan_u32(const uint32_t *in, const uint32_t *flags, uint32_t *out, uint
  *                     expansion instead of reading them (default 0)
  *   "sort_shape"      workgroup shape of radix passes that read arrays:
  *                     0 = 512 threads x 16 pairs, 1 = 256 x 16, 2 = 1024 x 8,
- *                     3 = 1024 x 16 (default)
+ *                     3 = 1024 x 16 (default), 4 = 1024 x 15
  * Outputs never depend on the knobs.  GRID_E_INVAL for an unknown key or value. */
 int grid_tune_set(const char *key, int value);
 int grid_tune_get(const char *key, int *value);

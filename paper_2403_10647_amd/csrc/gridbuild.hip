@@ -125,9 +125,10 @@ struct Plan {
 // expansion writes the object-order pairs and every pass reads arrays.
 int g_max_digit_bits = 9;
 int g_fused_expand = 0;
-int g_sort_shape = 3;  // radix passes from arrays: 0 = 512 x 16, 1 = 256 x 16, 2 = 1024 x 8, 3 = 1024 x 16
+int g_sort_shape = 3;  // radix passes from arrays: 0 = 512 x 16, 1 = 256 x 16, 2 = 1024 x 8, 3 = 1024 x 16,
+                       // 4 = 1024 x 15
 
-int sort_shape_tile(int shape) { return shape == 1 ? 4096 : shape == 3 ? 16384 : 8192; }
+int sort_shape_tile(int shape) { return shape == 1 ? 4096 : shape == 3 ? 16384 : shape == 4 ? 15360 : 8192; }
 
 Plan make_plan(uint32_t bits, int max_digit = -1) {
   Plan p{};
@@ -373,6 +374,9 @@ int launch_pass_rb(const SortPassArgs& a, bool regen, bool to_grids, uint32_t nt
       k<<<resident_blocks(k, 1024, ntiles), 1024, 0, s>>>(a);
     } else if (g_sort_shape == 3) {
       auto k = onesweep_kernel<1024, 16, RB, kFromArrays, kToArrays, B>;
+      k<<<resident_blocks(k, 1024, ntiles), 1024, 0, s>>>(a);
+    } else if (g_sort_shape == 4) {
+      auto k = onesweep_kernel<1024, 15, RB, kFromArrays, kToArrays, B>;
       k<<<resident_blocks(k, 1024, ntiles), 1024, 0, s>>>(a);
     } else {
       auto k = onesweep_kernel<kSortBlock, kSortK, RB, kFromArrays, kToArrays, B>;
@@ -1018,7 +1022,7 @@ int grid_tune_set(const char* key, int value) {
     return GRID_OK;
   }
   if (std::strcmp(key, "sort_shape") == 0) {
-    if (value < 0 || value > 3) return GRID_E_INVAL;
+    if (value < 0 || value > 4) return GRID_E_INVAL;
     g_sort_shape = value;
     return GRID_OK;
   }

@@ -65,13 +65,18 @@ __global__ __launch_bounds__(Block, Source == kFromArrays ? 4 : 2) void onesweep
       expand_tile<Block, K, Batched>(a.ex, tile, n, ntiles, s_stage, s_wtot, keys, vals);
     } else {
       // branch-free loads (the tail re-reads the last element) keep all of
-      // them in flight at once
+      // them in flight at once; the values are loaded after the rank, which
+      // does not need them
+      const uint32_t* kin = a.keys_in + base + w * (kWave * K) + lane;
+      if (nt == static_cast<uint32_t>(N)) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const uint32_t idx = w * (kWave * K) + k * kWave + lane;
-        const uint64_t src = base + (idx < nt ? idx : nt - 1);
-        keys[k] = a.keys_in[src];
-        vals[k] = a.vals_in[src];
+        for (int k = 0; k < K; ++k) keys[k] = kin[k * kWave];  // full tile: constant offsets
+      } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const uint32_t idx = w * (kWave * K) + k * kWave + lane;
+          keys[k] = a.keys_in[base + (idx < nt ? idx : nt - 1)];
+        }
       }
 #pragma unroll
       for (int k = 0; k < K; ++k) {
@@ -97,6 +102,19 @@ __global__ __launch_bounds__(Block, Source == kFromArrays ? 4 : 2) void onesweep
       if (valid && below == 0) s_cnt[w * R + d] = c + static_cast<uint32_t>(__builtin_popcountll(peers));
       __builtin_amdgcn_wave_barrier();
       rank[k] = c + below;
+    }
+    if constexpr (Source == kFromArrays) {
+      const uint32_t* vin = a.vals_in + base + w * (kWave * K) + lane;
+      if (nt == static_cast<uint32_t>(N)) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) vals[k] = vin[k * kWave];
+      } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const uint32_t idx = w * (kWave * K) + k * kWave + lane;
+          vals[k] = a.vals_in[base + (idx < nt ? idx : nt - 1)];
+        }
+      }
     }
     __syncthreads();
 

@@ -274,7 +274,7 @@ def test_build_under_every_tuning(G, fused, digit):
         G.tune_set("max_digit_bits", 9)
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
 def test_build_under_every_sort_shape(G, shape):
     G.tune_set("sort_shape", shape)
     try:
