@@ -268,6 +268,62 @@ GB_DEV uint32_t expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs,
   }
   uint32_t gcur = 0;
   if constexpr (Batched) gcur = grid_search<true>(a.gs, t0);
+  if constexpr (Layout == kBlocked) {
+    // A thread's K consecutive slots mostly belong to one object, and an owner
+    // that starts inside the run starts at offset 0, so GlobalCoords is only
+    // evaluated for the run's first slot and then stepped (x fastest) instead
+    // of dividing for every pair.  All K box loads are issued first.
+    uint64_t bx[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) bx[k] = a.box[t0 + (sv[k] >> 16)];
+    uint32_t x = 0, y = 0, z = 0;
+    {
+      const uint32_t ii = tid * K < n ? tid * K : n - 1;
+      const uint32_t v = sv[0];
+      const uint32_t rid = (v >> 16) == 0 ? static_cast<uint32_t>(base) + ii - s0 : ii - (v & 0xFFFFu);
+      const Box b = unpack_box(bx[0]);
+      const uint32_t mxy = b.m[0] * b.m[1];
+      z = rid / mxy;
+      const uint32_t r2 = rid - z * mxy;
+      y = r2 / b.m[0];
+      x = r2 - y * b.m[0];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t idx = tid * K + k;
+      const uint32_t obj = t0 + (sv[k] >> 16);
+      const Box b = unpack_box(bx[k]);
+      if (k > 0) {
+        if (sv[k] != sv[k - 1]) {
+          x = y = z = 0;  // a new owner starts here
+        } else {
+          ++x;
+          const bool cx = x == b.m[0];
+          x = cx ? 0u : x;
+          y += cx ? 1u : 0u;
+          const bool cy = y == b.m[1];
+          y = cy ? 0u : y;
+          z += cy ? 1u : 0u;
+        }
+      }
+      const uint32_t g = grid_of_tri<Batched>(a.gs, obj, gcur);
+      const GridDev& G = grid_at<Batched>(a.gs, g);
+      const uint32_t cell = (b.lo[0] + x) + G.res[0] * (b.lo[1] + y) + G.res[0] * G.res[1] * (b.lo[2] + z);
+      if constexpr (Batched) {
+        keys[k] = (g << a.gs.cell_bits) | cell;
+        vals[k] = obj - G.tri_base;
+      } else {
+        keys[k] = cell;
+        vals[k] = obj;
+      }
+      if (idx >= n) {
+        keys[k] = 0xFFFFFFFFu;
+        vals[k] = 0;
+      }
+    }
+    __syncthreads();
+    return n;
+  }
   // items in chunks: all box gathers of a chunk are in flight together, while
   // the live registers stay bounded
   constexpr int KC = K >= 8 ? 8 : K;
@@ -341,7 +397,7 @@ struct ExpandOutArgs {
 };
 
 template <int Block, int K, int RB, bool Batched>
-__global__ __launch_bounds__(Block) void expand_kernel(ExpandOutArgs a) {
+__global__ __launch_bounds__(Block, 4) void expand_kernel(ExpandOutArgs a) {
   constexpr int N = Block * K;
   constexpr int R = RB > 0 ? 1 << RB : 1;
   static_assert(K % 4 == 0, "items are stored four at a time");
