@@ -7,8 +7,11 @@ A step is one pass of the whole build (count + scan, expansion, radix sort,
 ranges) over a device-resident scene, through the C ABI.  The line printed is
 one JSON object with ms/build, Mpairs/s, the dominant kernel's HBM roofline
 (its algorithmic bytes over its event-timed duration) and the CPU oracle's
-rate on the same workload.  ``--batched`` adds the 512-grid batched build
-against 512 one-at-a-time plain builds.
+rate on the same workload, with the GPU grid compared to the oracle's grid.
+Unless switched off it also times the 512-grid batched build (eager and as a
+replayed graph) against 512 one-at-a-time plain builds, and serves Poisson
+arrivals of requests shaped like those grids, plus the 10M-triangle scene once a
+second, through the continuous-batching server (p50/p99 latency, builds/s).
 
 Other modes (for the counter calibration of profiles):
     python bench.py --mode copy      plain device copy of 1 GiB, 10 times
@@ -66,16 +69,22 @@ def load_traffic(kernel: str, workload: str):
     return e.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(scene, npairs: int) -> dict:
+def cpu_baseline(scene, npairs: int, gpu_out) -> dict:
+    """The oracle timed on one host core over the whole workload; its grid is then compared
+    with the GPU's, element by element."""
+    import numpy as np
     import oracle
     assert oracle.probe_npairs(scene.verts, scene.tris, scene.lo, scene.hi, scene.res) == npairs
     t0 = time.perf_counter()
     c, o, r = oracle.build(scene.verts, scene.tris, scene.lo, scene.hi, scene.res, npairs=npairs)
     dt = time.perf_counter() - t0
     assert len(c) == npairs
+    gc, go, gr = gpu_out.numpy()
+    same = bool(np.array_equal(c, gc) and np.array_equal(o, go) and np.array_equal(r, gr))
     return {"value": round(npairs / dt / 1e6, 3), "unit": "Mpairs/s", "cores": 1, "kind": "oracle",
             "sample": f"the full workload, one serial build ({scene.ntris} triangles, {npairs} pairs) "
-                      f"in {dt:.2f} s on {platform.processor() or platform.machine()}, {os.cpu_count()} host cores"}
+                      f"in {dt:.2f} s on {platform.processor() or platform.machine()}, {os.cpu_count()} host cores",
+            "gpu_grid_identical": same}
 
 
 def run_copy(steps: int):
@@ -129,13 +138,78 @@ def run_batched(G, args) -> dict:
             G.build(g, out=o, ws=ws_p)
     torch.cuda.synchronize()
     tp = (time.perf_counter() - t0) / reps
-    same = all(torch.equal(a.cells[:a.npairs], b.cells[:b.npairs]) and torch.equal(a.objs[:a.npairs], b.objs[:b.npairs])
-               and torch.equal(a.ranges, b.ranges) for a, b in zip(outs_b, outs_p))
+    # the same batch as one captured graph of the asynchronous build, replayed
+    outs_g = G.alloc_results(inputs, caps)
+    ws_g = G.Workspace()
+    stage = torch.empty(int(G.lib().grid_batch_staging_size(len(inputs))), dtype=torch.uint8, pin_memory=True)
+    sg = torch.cuda.Stream()
+    G.build_batched_async(inputs, outs_g, caps, ws_g, stage, stream=sg)
+    sg.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=sg):
+        G.build_batched_async(inputs, outs_g, caps, ws_g, stage, stream=sg)
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        graph.replay()
+    torch.cuda.synchronize()
+    tg = (time.perf_counter() - t0) / reps
+    g_status = G.workspace_status(ws_g)[0]
+
+    def same_as_plain(outs):
+        return all(torch.equal(a.cells[:a.npairs], b.cells[:b.npairs]) and torch.equal(a.objs[:a.npairs], b.objs[:b.npairs])
+                   and torch.equal(a.ranges, b.ranges) for a, b in zip(outs, outs_p))
+    same = same_as_plain(outs_b)
+    same_g = g_status == G.GRID_OK and same_as_plain(outs_g)
     ntot = sum(caps)
-    return {"ngrids": len(inputs), "triangles": int(sum(s.ntris for s in batch)), "npairs": int(ntot),
-            "batched_builds_per_s": round(len(inputs) / tb, 1), "plain_builds_per_s": round(len(inputs) / tp, 1),
-            "batched_ms": round(tb * 1e3, 3), "plain_ms": round(tp * 1e3, 3), "speedup": round(tp / tb, 3),
-            "identical_outputs": bool(same), "generation_s": round(gen_s, 1)}
+    res = {"ngrids": len(inputs), "triangles": int(sum(s.ntris for s in batch)), "npairs": int(ntot),
+           "batched_builds_per_s": round(len(inputs) / tb, 1), "plain_builds_per_s": round(len(inputs) / tp, 1),
+           "graph_builds_per_s": round(len(inputs) / tg, 1),
+           "batched_ms": round(tb * 1e3, 3), "graph_ms": round(tg * 1e3, 3), "plain_ms": round(tp * 1e3, 3),
+           "speedup": round(tp / tb, 3), "graph_speedup": round(tp / tg, 3),
+           "identical_outputs": bool(same), "graph_identical_outputs": bool(same_g), "generation_s": round(gen_s, 1)}
+    del outs_b, outs_g, ws_g, ws_b
+    torch.cuda.empty_cache()
+    return res, inputs, outs_p
+
+
+def run_served(G, args, pool, pool_refs, big, big_ref) -> dict:
+    """Poisson arrivals of requests drawn from the batch's grids plus the 10M-triangle scene once a
+    second, through the continuous-batching server; every output is compared on the device with the
+    same scene's stand-alone build.  Then the same kind of requests all at once (burst), under the
+    full budget and under a tight one, against one-at-a-time plain builds."""
+    import torch
+    from paper_2403_10647_amd import serve
+    refs = list(pool_refs) + [big_ref]
+    big_key = len(pool)
+    ws = serve.batch_workspace_bytes([big], [big_ref.npairs])
+    budget = args.serve_budget_gb << 30
+    srv = serve.Server(budget, ws, nslots=args.serve_slots, max_pairs=args.serve_max_pairs, references=refs)
+    warm = serve.make_requests(pool, rate=2000.0, duration=0.2, seed=args.seed + 100, big=big, big_key=big_key)
+    srv.run(warm)
+    reqs = serve.make_requests(pool, rate=args.serve_rate, duration=args.serve_seconds, seed=args.seed, big=big,
+                               big_every=1.0, big_key=big_key)
+    print(f"# serving {len(reqs)} requests over {args.serve_seconds} s", file=sys.stderr, flush=True)
+    st = srv.run(reqs).as_dict()
+    burst = serve.make_requests(pool, rate=2000.0, duration=1.0, seed=args.seed + 1, big=big, big_key=big_key,
+                                burst=True)
+    sb = srv.run(burst).as_dict()
+    del srv
+    torch.cuda.empty_cache()
+    big_out = serve.output_bytes(big_ref.npairs, big.ncells)
+    tight = 2 * ws + big_out + (256 << 20)
+    srv_t = serve.Server(tight, ws, nslots=2, max_pairs=args.serve_max_pairs, references=refs)
+    stt = srv_t.run(burst).as_dict()
+    del srv_t
+    torch.cuda.empty_cache()
+    plain = serve.plain_builds_per_s(burst)
+    ok = st["mismatches"] == 0 and sb["mismatches"] == 0 and stt["mismatches"] == 0
+    return {"open_loop": {"rate_per_s": args.serve_rate, "big_every_s": 1.0, **st},
+            "burst": sb, "burst_tight_budget": stt,
+            "burst_plain_builds_per_s": round(plain["builds_per_s"], 1),
+            "burst_speedup_vs_plain": round(sb["builds_per_s"] / plain["builds_per_s"], 3),
+            "slot_workspace_bytes": ws, "all_outputs_identical_to_alone": bool(ok)}
 
 
 def main():
@@ -146,7 +220,13 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workload", default="arch", choices=["arch", "mixed", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batched", action="store_true", help="also time the 512-grid batched build")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-grid batched build and serving")
+    ap.add_argument("--no-serve", action="store_true", help="skip serving")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-budget-gb", type=int, default=64)
+    ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--serve-max-pairs", type=int, default=1 << 25)
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--ngrids", type=int, default=512)
     ap.add_argument("--no-trace", action="store_true", help="time without per-kernel events")
@@ -257,10 +337,16 @@ def main():
         "pipeline": pipeline,
         "cpu_baseline": None,
     }
-    if args.batched:
-        result["batched"] = run_batched(G, args)
+    if not args.no_batched:
+        print("# batched", file=sys.stderr, flush=True)
+        result["batched"], pool, pool_refs = run_batched(G, args)
+        if not args.no_serve:
+            print("# serving", file=sys.stderr, flush=True)
+            result["served"] = run_served(G, args, pool, pool_refs, gin, out)
+        del pool, pool_refs
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(scene, NO)
+        print("# cpu baseline", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(scene, NO, out)
     print(json.dumps(result), flush=True)
 
 

@@ -133,6 +133,25 @@ int grid_count_batched(grid_desc *grids, uint32_t ngrids, void *ws, size_t ws_by
  * then set) and builds nothing.  Synchronizes stream once, after the count. */
 int grid_build_batched(grid_desc *grids, uint32_t ngrids, void *ws, size_t ws_bytes, void *stream);
 
+/* Batched build with no host synchronisation, for overlapping batches on
+ * several streams (serving) and for stream capture.  Every grid's
+ * out.cap_pairs must already hold at least its NO (from grid_count_batched);
+ * the batch's packed keys must fit in 32 bits (GRID_E_INVAL otherwise: split
+ * the batch).  host_staging is caller-owned pinned host memory of at least
+ * grid_batch_staging_size(ngrids) bytes, which must stay untouched until the
+ * stream has passed this call.  Errors found on the device (a bad vertex
+ * index, a count above capacity, NO above 2^32 - 1) stop every later kernel
+ * before it writes; grid_workspace_status reports them.  out.npairs is not
+ * written (the counts are the caller's capacities). */
+size_t grid_batch_staging_size(uint32_t ngrids);
+int grid_build_batched_async(const grid_desc *grids, uint32_t ngrids, void *ws, size_t ws_bytes,
+                             void *host_staging, size_t staging_bytes, void *stream);
+
+/* Status of the last build launched on a workspace (the device-side flags of
+ * grid_build_batched_async) and, if npairs_total (host) is not NULL, its total
+ * pair count.  Synchronizes stream. */
+int grid_workspace_status(const void *ws, uint64_t *npairs_total, void *stream);
+
 /* ---- building blocks, exposed for testing and reuse ------------------------ */
 
 /* Stable LSD radix sort of (keys, vals) by the low nbits bits of keys

@@ -35,6 +35,7 @@ EXPORTS = (
     "grid_workspace_size_batched", "grid_count_batched", "grid_build_batched",
     "grid_sort_workspace_size", "grid_sort_pairs", "grid_scan_workspace_size", "grid_scan_u32",
     "grid_trace_enable", "grid_trace_read", "grid_tune_set", "grid_tune_get", "grid_sort_plan",
+    "grid_batch_staging_size", "grid_build_batched_async", "grid_workspace_status",
 )
 
 
@@ -93,6 +94,12 @@ def lib():
         L.grid_scan_workspace_size.argtypes = [U64]
         L.grid_scan_workspace_size.restype = SZ
         L.grid_scan_u32.argtypes = [P, P, P, U64, C.c_int, P, SZ, C.POINTER(C.c_uint64), P]
+        L.grid_batch_staging_size.argtypes = [U32]
+        L.grid_batch_staging_size.restype = SZ
+        L.grid_build_batched_async.argtypes = [C.POINTER(grid_desc), U32, P, SZ, P, SZ, P]
+        L.grid_build_batched_async.restype = C.c_int
+        L.grid_workspace_status.argtypes = [P, C.POINTER(C.c_uint64), P]
+        L.grid_workspace_status.restype = C.c_int
         L.grid_tune_set.argtypes = [C.c_char_p, C.c_int]
         L.grid_tune_get.argtypes = [C.c_char_p, C.POINTER(C.c_int)]
         L.grid_tune_set.restype = C.c_int
@@ -367,3 +374,31 @@ def sort_plan(nbits: int):
     w = (C.c_uint32 * 4)()
     _check(lib().grid_sort_plan(nbits, C.byref(p), w, C.byref(k)), "grid_sort_plan")
     return int(p.value), [int(w[i]) for i in range(p.value)], int(k.value)
+
+
+def build_batched_async(inputs: List[GridInput], outs: List[GridResult], npairs: List[int], ws: Workspace,
+                        staging: torch.Tensor, stream=None):
+    """Launch a batched build without waiting.
+
+    ``npairs`` are the grids' pair counts from count_batched; each output must hold at least that
+    many pairs.  ``staging`` is a pinned host uint8 tensor of at least grid_batch_staging_size(n)
+    bytes that must stay untouched until the stream passes this call.  Errors found on the device
+    are read later with workspace_status(ws)."""
+    L = lib()
+    arr = _descs(inputs, outs)
+    n = len(inputs)
+    need = int(L.grid_batch_staging_size(n))
+    assert staging.is_pinned() and staging.numel() >= need
+    wp, wn = ws.ptr_size(L.grid_workspace_size_batched(arr, n))
+    st = L.grid_build_batched_async(arr, n, wp, wn, C.c_void_p(staging.data_ptr()), C.c_size_t(staging.numel()),
+                                    _stream(stream))
+    _check(st, "grid_build_batched_async")
+    for o, c in zip(outs, npairs):
+        o.npairs = int(c)
+
+
+def workspace_status(ws: Workspace, stream=None):
+    """(status, total NO) of the last build launched on ws (waits for the stream)."""
+    tot = C.c_uint64(0)
+    st = lib().grid_workspace_status(C.c_void_p(ws.buf.data_ptr()), C.byref(tot), _stream(stream))
+    return int(st), int(tot.value)

@@ -23,10 +23,16 @@ struct Control {
   uint32_t tile_counter[16];   // dynamic tile ids, one per kernel of the sequence
   uint64_t npairs;             // NO, written by the last count tile
   uint32_t error;              // bit 0: bad vertex index
-  uint32_t pad0;
+  uint32_t cap_flag;           // set when some grid's NO exceeds its capacity
   uint64_t scratch[4];
 };
 constexpr uint32_t kErrBadIndex = 1u;
+
+// After the count, a build whose inputs were rejected on the device (a bad
+// vertex index, a pair count above capacity) writes nothing more: every later
+// kernel checks this first.  Host-synchronised builds never get here with an
+// error; builds launched without a readback rely on it.
+GB_DEV bool build_failed(const Control* c) { return (c->error | c->cap_flag) != 0; }
 
 GB_DEV uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 

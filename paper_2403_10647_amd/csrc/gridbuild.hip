@@ -282,7 +282,7 @@ int launch_plan(Build& b) {
   a.merge_tile = kMergeTile;
   a.run = at<GridRun>(b.ws, b.L.run);
   a.npairs_out = at<uint64_t>(b.ws, b.L.npairs_out);
-  a.cap_flag = &at<Control>(b.ws, b.L.ctl)->pad0;
+  a.cap_flag = &at<Control>(b.ws, b.L.ctl)->cap_flag;
   a.ctl = at<Control>(b.ws, b.L.ctl);
   TraceScope ts(b.s, "plan");
   plan_kernel<kPlanBlock, B><<<1, kPlanBlock, 0, b.s>>>(a);
@@ -532,7 +532,7 @@ int read_ctl(const Build& b, HostCtl* h) {
   GB_TRY(hipStreamSynchronize(b.s));
   h->npairs = c.npairs;
   h->error = c.error;
-  h->cap_flag = c.pad0;
+  h->cap_flag = c.cap_flag;
   return GRID_OK;
 }
 
@@ -706,7 +706,7 @@ uint32_t batch_chunk(const grid_desc* grids, uint32_t ngrids, uint32_t g0) {
 }
 
 int prepare_batched(Build& b, BatchSetup& bs, const grid_desc* grids, uint32_t ngrids, void* ws, size_t ws_bytes,
-                    hipStream_t s, bool need_out) {
+                    hipStream_t s, bool need_out, void* staging = nullptr, size_t staging_bytes = 0) {
   int st = setup_batch(grids, ngrids, &bs, need_out);
   if (st) return st;
   if (bs.cell_bits + bs.grid_bits > 32) return GRID_E_INVAL;
@@ -722,8 +722,16 @@ int prepare_batched(Build& b, BatchSetup& bs, const grid_desc* grids, uint32_t n
   b.gs.table = at<GridDev>(ws, b.L.table);
   b.gs.ngrids = ngrids;
   b.gs.cell_bits = bs.cell_bits;
-  GB_TRY(hipMemcpyAsync(at<GridDev>(ws, b.L.table), bs.table.data(), ngrids * sizeof(GridDev),
-                        hipMemcpyHostToDevice, s));
+  if (staging) {
+    // caller-owned pinned memory: the copy stays asynchronous
+    if (staging_bytes < ngrids * sizeof(GridDev)) return GRID_E_NOMEM;
+    std::memcpy(staging, bs.table.data(), ngrids * sizeof(GridDev));
+    GB_TRY(hipMemcpyAsync(at<GridDev>(ws, b.L.table), staging, ngrids * sizeof(GridDev), hipMemcpyHostToDevice, s));
+  } else {
+    // the caller synchronises before bs goes away (the count readback)
+    GB_TRY(hipMemcpyAsync(at<GridDev>(ws, b.L.table), bs.table.data(), ngrids * sizeof(GridDev),
+                          hipMemcpyHostToDevice, s));
+  }
   return GRID_OK;
 }
 
@@ -1045,6 +1053,48 @@ int grid_tune_get(const char* key, int* value) {
   if (std::strcmp(key, "fused_expand") == 0) { *value = g_fused_expand; return GRID_OK; }
   if (std::strcmp(key, "sort_shape") == 0) { *value = g_sort_shape; return GRID_OK; }
   return GRID_E_INVAL;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// Batched builds without a host readback.
+// ---------------------------------------------------------------------------------
+extern "C" {
+
+size_t grid_batch_staging_size(uint32_t ngrids) { return static_cast<size_t>(ngrids) * sizeof(GridDev); }
+
+int grid_build_batched_async(const grid_desc* grids, uint32_t ngrids, void* ws, size_t ws_bytes, void* host_staging,
+                             size_t staging_bytes, void* stream) {
+  if (!grids || ngrids == 0 || !host_staging) return GRID_E_INVAL;
+  if (batch_chunk(grids, ngrids, 0) != ngrids) return GRID_E_INVAL;  // packed keys must fit in 32 bits
+  Build b{};
+  BatchSetup bs;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int st = prepare_batched(b, bs, grids, ngrids, ws, ws_bytes, s, true, host_staging, staging_bytes);
+  if (st) return st;
+  if ((st = launch_zero(b.ws, b.L.zero_end, s))) return st;
+  if ((st = launch_count<true>(b))) return st;
+  if ((st = launch_plan<true>(b))) return st;
+  // sizes on the host are the capacities; the kernels read the true counts
+  if (bs.cap > 0) {
+    if (b.plan.sp.passes == 0) return GRID_E_INVAL;
+    if ((st = launch_sort<true>(b, nullptr, nullptr, bs.cap))) return st;
+  }
+  return launch_ranges<true>(b, bs.cells + ngrids + bs.cap);
+}
+
+int grid_workspace_status(const void* ws, uint64_t* npairs_total, void* stream) {
+  if (!ws) return GRID_E_INVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Control c;  // the control block opens every workspace
+  GB_TRY(hipMemcpyAsync(&c, ws, sizeof(Control), hipMemcpyDeviceToHost, s));
+  GB_TRY(hipStreamSynchronize(s));
+  if (npairs_total) *npairs_total = c.npairs;
+  if (c.error & kErrBadIndex) return GRID_E_BADINDEX;
+  if (c.cap_flag & 2u) return GRID_E_OVERFLOW;
+  if (c.cap_flag & 1u) return GRID_E_CAPACITY;
+  return GRID_OK;
 }
 
 }  // extern "C"

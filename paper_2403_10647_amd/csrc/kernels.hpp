@@ -405,6 +405,7 @@ __global__ __launch_bounds__(Block, 4) void expand_kernel(ExpandOutArgs a) {
   __shared__ uint32_t s_hist[RB > 0 ? 4 * R : 1];
   __shared__ uint32_t s_wtot[Block / kWave];
   __shared__ uint32_t s_tile;
+  if (build_failed(a.ctl)) return;
   const uint64_t npairs = a.ctl->npairs;
   const uint32_t ntiles = static_cast<uint32_t>((npairs + N - 1) / N);
   if constexpr (RB > 0) {
@@ -492,6 +493,7 @@ __global__ __launch_bounds__(Block) void hist_kernel(HistArgs a) {
   __shared__ uint32_t s_hist[4 * R];
   __shared__ uint32_t s_wtot[Block / kWave];
   __shared__ uint32_t s_tile;
+  if (build_failed(a.ctl)) return;
   const uint64_t npairs = a.ctl->npairs;
   const uint32_t ntiles = static_cast<uint32_t>((npairs + N - 1) / N);
   // clear the sort passes' look-back words

@@ -39,6 +39,7 @@ __global__ __launch_bounds__(Block) void plan_kernel(PlanArgs a) {
   __shared__ uint32_t s_wtot[Block / kWave];
   const uint64_t total = a.ctl->npairs;
   const uint32_t G = a.gs.ngrids;
+  if (threadIdx.x == 0 && total > 0xFFFFFFFFull) atomicOr(a.cap_flag, 2u);  // 32-bit pair indices overflow
   for (uint32_t g = threadIdx.x; g < G; g += Block) {
     const uint32_t tb = grid_at<Batched>(a.gs, g).tri_base;
     a.run[g].pair_base = tb < a.ntris ? a.start[tb] : total;
@@ -101,6 +102,7 @@ GB_DEV uint32_t merge_split(const uint32_t* cells, uint64_t npairs, uint64_t nev
 
 template <int Block, bool Batched>
 __global__ __launch_bounds__(Block) void split_kernel(RangesArgs a) {
+  if (build_failed(a.ctl)) return;
   const uint32_t G = a.gs.ngrids;
   const uint32_t total = a.run[G].mtile_base;
   for (uint32_t b = blockIdx.x * Block + threadIdx.x; b < total; b += gridDim.x * Block) {
@@ -117,6 +119,7 @@ __global__ __launch_bounds__(Block) void ranges_kernel(RangesArgs a) {
   constexpr int D = Block * K;
   __shared__ uint32_t s_cells[D];
   __shared__ uint32_t s_begin[D];
+  if (build_failed(a.ctl)) return;
   const uint32_t G = a.gs.ngrids;
   const uint32_t total = a.run[G].mtile_base;
   const uint32_t tid = threadIdx.x;

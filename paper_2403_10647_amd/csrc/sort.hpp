@@ -47,6 +47,7 @@ __global__ __launch_bounds__(Block, Source == kFromArrays ? 4 : 2) void onesweep
   __shared__ uint32_t s_wtot[W];
   __shared__ uint32_t s_tile;
 
+  if (a.n_from_ctl && build_failed(a.ctl)) return;
   const uint64_t n = a.n_from_ctl ? a.ctl->npairs : a.n;
   const uint32_t ntiles = static_cast<uint32_t>((n + N - 1) / N);
   const uint32_t tid = threadIdx.x;

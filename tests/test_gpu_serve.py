@@ -1,0 +1,113 @@
+"""GPU checks of the continuous-batching server: every request served in the mix
+equals the same scene built alone (and the oracle), whatever the budget, and a
+request larger than the budget is rejected without disturbing the others."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_10647_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_10647_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+@pytest.fixture(scope="module")
+def workload(G):
+    rng = np.random.default_rng(31)
+    pool_scenes = scenes.make_batch(31, ngrids=16, sizes=rng.integers(1000, 30_000, size=16))
+    big_scene = scenes.make_scene("arch", seed=3, ntris=300_000)
+    pool = [G.GridInput.from_scene(s) for s in pool_scenes]
+    big = G.GridInput.from_scene(big_scene)
+    refs = [G.build(g) for g in pool] + [G.build(big)]
+    torch.cuda.synchronize()
+    return pool_scenes, big_scene, pool, big, refs
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _server(G, serve, pool, big, refs, budget, nslots=3):
+    caps = [r.npairs for r in refs]
+    ws = max(serve.batch_workspace_bytes([big], [caps[-1]]), serve.batch_workspace_bytes(pool, caps[:-1]))
+    return serve.Server(budget, ws, nslots=nslots, max_pairs=1 << 20, references=refs, keep_results=True)
+
+
+def _check_alone(G, reqs, refs):
+    for r in reqs:
+        ref = refs[r.key]
+        assert r.status == G.GRID_OK, r.rid
+        assert r.result.npairs == ref.npairs
+        n = ref.npairs
+        assert torch.equal(r.result.cells[:n], ref.cells[:n]), r.rid
+        assert torch.equal(r.result.objs[:n], ref.objs[:n]), r.rid
+        assert torch.equal(r.result.ranges, ref.ranges), r.rid
+
+
+def test_refs_match_oracle(G, workload):
+    pool_scenes, big_scene, pool, big, refs = workload
+    for i in (0, 7, 15):
+        c, o, r = refs[i].numpy()
+        oc, oo, orr = oracle.build_scene(pool_scenes[i])
+        assert np.array_equal(c, oc) and np.array_equal(o, oo) and np.array_equal(r, orr)
+    c, o, r = refs[-1].numpy()
+    oc, oo, orr = oracle.build_scene(big_scene)
+    assert np.array_equal(c, oc) and np.array_equal(o, oo) and np.array_equal(r, orr)
+
+
+def test_served_in_the_mix_equals_alone(G, workload):
+    from paper_2403_10647_amd import serve
+    _, _, pool, big, refs = workload
+    reqs = serve.make_requests(pool, rate=3000.0, duration=0.3, seed=7, big=big, big_every=0.1, big_key=len(pool))
+    _say("serve mix", len(reqs))
+    srv = _server(G, serve, pool, big, refs, budget=8 << 30)
+    st = srv.run(reqs)
+    _say(st.as_dict())
+    assert st.completed == len(reqs) and st.rejected == 0 and st.failed == 0
+    assert st.mismatches == 0 and st.verified == len(reqs)
+    assert st.batches < len(reqs)          # requests were batched together
+    _check_alone(G, reqs, refs)
+
+
+def test_burst_under_a_tight_budget(G, workload):
+    from paper_2403_10647_amd import serve
+    _, _, pool, big, refs = workload
+    reqs = serve.make_requests(pool, rate=2000.0, duration=0.1, seed=8, big=big, big_every=0.05, big_key=len(pool),
+                               burst=True)
+    caps = [r.npairs for r in refs]
+    ws = max(serve.batch_workspace_bytes([big], [caps[-1]]), serve.batch_workspace_bytes(pool, caps[:-1]))
+    big_out = serve.output_bytes(refs[-1].npairs, big.ncells)
+    budget = 2 * ws + big_out + (1 << 20)  # room for the big request's outputs and little else
+    _say("serve tight", len(reqs), budget)
+    srv = serve.Server(budget, ws, nslots=2, max_pairs=1 << 20, references=refs, keep_results=True)
+    st = srv.run(reqs)
+    _say(st.as_dict())
+    assert st.completed == len(reqs) and st.mismatches == 0
+    assert st.peak_bytes <= budget - 2 * ws
+    _check_alone(G, reqs, refs)
+
+
+def test_request_above_budget_is_rejected(G, workload):
+    from paper_2403_10647_amd import serve
+    _, _, pool, big, refs = workload
+    reqs = serve.make_requests(pool, rate=2000.0, duration=0.05, seed=9, big=big, big_every=1.0, big_key=len(pool))
+    caps = [r.npairs for r in refs]
+    ws = serve.batch_workspace_bytes(pool, caps[:-1])
+    big_out = serve.output_bytes(refs[-1].npairs, big.ncells)
+    srv = serve.Server(2 * ws + big_out // 2, ws, nslots=2, max_pairs=1 << 20, references=refs, keep_results=True)
+    st = srv.run(reqs)
+    _say(st.as_dict())
+    assert st.rejected == 1 and st.completed == len(reqs) - 1 and st.mismatches == 0
+    rej = [r for r in reqs if r.status != G.GRID_OK]
+    assert len(rej) == 1 and rej[0].key == len(pool) and rej[0].status == G.GRID_E_NOMEM
+    _check_alone(G, [r for r in reqs if r.status == G.GRID_OK], refs)
