@@ -138,6 +138,13 @@ def run_batched(G, args) -> dict:
             G.build(g, out=o, ws=ws_p)
     torch.cuda.synchronize()
     tp = (time.perf_counter() - t0) / reps
+    # one more batched build with per-kernel events, outside the timed region
+    G.trace_enable(True)
+    G.trace_read()
+    G.build_batched(inputs, outs_b, ws_b)
+    kern = G.trace_read()
+    G.trace_enable(False)
+    batched_kernels = {k: {"launches": v[0], "ms": round(v[1], 4)} for k, v in sorted(kern.items(), key=lambda kv: -kv[1][1])}
     # the same batch as one captured graph of the asynchronous build, replayed
     outs_g = G.alloc_results(inputs, caps)
     ws_g = G.Workspace()
@@ -168,7 +175,9 @@ def run_batched(G, args) -> dict:
            "graph_builds_per_s": round(len(inputs) / tg, 1),
            "batched_ms": round(tb * 1e3, 3), "graph_ms": round(tg * 1e3, 3), "plain_ms": round(tp * 1e3, 3),
            "speedup": round(tp / tb, 3), "graph_speedup": round(tp / tg, 3),
-           "identical_outputs": bool(same), "graph_identical_outputs": bool(same_g), "generation_s": round(gen_s, 1)}
+           "identical_outputs": bool(same), "graph_identical_outputs": bool(same_g), "generation_s": round(gen_s, 1),
+           "sort_plan": G.sort_plan(max(1, (sum(g.ncells for g in inputs) - 1).bit_length())),
+           "kernels": batched_kernels}
     del outs_b, outs_g, ws_g, ws_b
     torch.cuda.empty_cache()
     return res, inputs, outs_p

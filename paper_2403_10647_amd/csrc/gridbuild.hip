@@ -30,6 +30,7 @@ constexpr int kMergeTile = kRangesBlock * kRangesK;
 constexpr int kScanBlock = 256, kScanK = 8;
 constexpr int kPlanBlock = 1024;
 constexpr int kMaxRadixBits = 11;
+constexpr int kKeyMapBits = 13;                         // batched key map: at most 8192 buckets
 static_assert((1 << kSortTileShift) == kSortTile, "sort tile must be a power of two");
 
 #define GB_TRY(expr)                             \
@@ -154,7 +155,8 @@ Plan make_plan(uint32_t bits, int max_digit = -1) {
 // ---- workspace layout -----------------------------------------------------------
 struct Layout {
   size_t ctl, hist, count_status, zero_end;
-  size_t start, box, tfo, sort_status, keys_alt, vals_alt, keys_alt2, vals_alt2, run, npairs_out, splits, table, total;
+  size_t start, box, tfo, tfg, sort_status, keys_alt, vals_alt, keys_alt2, vals_alt2, run, npairs_out, splits, table, sink,
+      kmap, total;
   uint32_t ntfo, ncount_tiles, nsort_tiles_cap, nmerge_tiles_cap;
 };
 
@@ -178,6 +180,7 @@ Layout make_layout(uint64_t ntris, uint64_t cap_pairs, uint64_t ncells_plus_grid
   L.start = take(ntris * 4);
   L.box = take(ntris * 8);
   L.tfo = take(static_cast<size_t>(L.ntfo) * 4);
+  L.tfg = take(batched ? static_cast<size_t>(L.ntfo) * 4 : 0);
   L.sort_status = take(static_cast<size_t>(plan.sp.passes) * L.nsort_tiles_cap * (size_t{1} << plan.rb) * 8);
   L.keys_alt = take(cap_pairs * 4);
   L.vals_alt = take(cap_pairs * 4);
@@ -189,6 +192,8 @@ Layout make_layout(uint64_t ntris, uint64_t cap_pairs, uint64_t ncells_plus_grid
   L.npairs_out = take(ngrids * 8);
   L.splits = take(static_cast<size_t>(L.nmerge_tiles_cap) * 4);
   L.table = take(batched ? ngrids * sizeof(GridDev) : 0);
+  L.sink = take(batched ? ngrids * sizeof(GridSink) : 0);
+  L.kmap = take(batched ? (size_t{1} << kKeyMapBits) * sizeof(uint2) : 0);
   L.total = o + 256;
   return L;
 }
@@ -251,6 +256,7 @@ struct Build {
   GridSet gs;
   uint32_t ntris;
   bool batched;
+  uint64_t batch_cells;  // batched: cells of all grids (the sort-key space)
   hipStream_t s;
 };
 
@@ -263,6 +269,7 @@ int launch_count(Build& b) {
   a.start = at<uint32_t>(b.ws, b.L.start);
   a.box = at<uint64_t>(b.ws, b.L.box);
   a.tfo = at<uint32_t>(b.ws, b.L.tfo);
+  a.tfg = at<uint32_t>(b.ws, b.L.tfg);
   a.ntfo = b.L.ntfo;
   a.sort_tile_shift = kSortTileShift;
   a.status = at<uint64_t>(b.ws, b.L.count_status);
@@ -296,6 +303,7 @@ ExpandArgs expand_args(const Build& b) {
   e.start = at<uint32_t>(b.ws, b.L.start);
   e.box = at<uint64_t>(b.ws, b.L.box);
   e.tfo = at<uint32_t>(b.ws, b.L.tfo);
+  e.tfg = at<uint32_t>(b.ws, b.L.tfg);
   e.ntris = b.ntris;
   return e;
 }
@@ -341,10 +349,19 @@ int launch_expand(Build& b, uint32_t* cells, uint32_t* objs, uint64_t npairs) {
   a.clear_tile = kSortTileMin;
   a.vec16 = ((reinterpret_cast<uintptr_t>(cells) | reinterpret_cast<uintptr_t>(objs)) & 15u) == 0;
   a.ctl = at<Control>(b.ws, b.L.ctl);
-  TraceScope ts(b.s, RB > 0 ? "expand_hist" : "expand");
-  auto kern = expand_kernel<kSortBlock, kSortK, RB, B>;
-  kern<<<resident_blocks(kern, kSortBlock, ceil_div(npairs, kSortTile)), kSortBlock, 0, b.s>>>(a);
-  GB_LAUNCHED();
+  {
+    TraceScope ts(b.s, RB > 0 ? "expand_hist" : "expand");
+    auto kern = expand_kernel<kSortBlock, kSortK, RB, B>;
+    kern<<<resident_blocks(kern, kSortBlock, ceil_div(npairs, kSortTile)), kSortBlock, 0, b.s>>>(a);
+    GB_LAUNCHED();
+  }
+  if constexpr (B) {
+    // the tiles that straddle grids, skipped above
+    TraceScope ts(b.s, "expand_straddle");
+    auto kern = expand_straddle_kernel<kSortBlock, kSortK, RB>;
+    kern<<<static_cast<uint32_t>(std::min<uint64_t>(ceil_div(npairs, kSortTile), 1024)), kSortBlock, 0, b.s>>>(a);
+    GB_LAUNCHED();
+  }
   return GRID_OK;
 }
 
@@ -418,9 +435,32 @@ Dest sort_dest(const Build& b, bool batched, int i, uint32_t P, uint32_t* out_k,
   return to_out ? Dest{out_k, out_v} : Dest{ak, av};
 }
 
+// Batched builds: the per-grid sinks and the key map of the last radix pass.
+int launch_sink(Build& b) {
+  const uint32_t kbits = bits_for(b.batch_cells);
+  SinkArgs a{};
+  a.gs = b.gs;
+  a.run = at<GridRun>(b.ws, b.L.run);
+  a.sink = at<GridSink>(b.ws, b.L.sink);
+  a.kmap = at<uint2>(b.ws, b.L.kmap);
+  a.kshift = kbits > static_cast<uint32_t>(kKeyMapBits) ? kbits - kKeyMapBits : 0;
+  a.ncells = b.batch_cells;
+  a.nbuckets = static_cast<uint32_t>(((b.batch_cells - 1) >> a.kshift) + 1);
+  if (b.batch_cells == 0 || a.nbuckets > (1u << kKeyMapBits)) return GRID_E_INVAL;
+  const uint32_t items = std::max(a.nbuckets, b.gs.ngrids);
+  TraceScope ts(b.s, "sink");
+  sink_kernel<256><<<static_cast<uint32_t>(std::min<uint64_t>(ceil_div(items, 256), 1024)), 256, 0, b.s>>>(a);
+  GB_LAUNCHED();
+  return GRID_OK;
+}
+
 template <int RB, bool B>
 int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t npairs) {
   const SortPlan& sp = b.plan.sp;
+  if constexpr (B) {
+    int st = launch_sink(b);
+    if (st) return st;
+  }
   const uint32_t ntiles = static_cast<uint32_t>(ceil_div(npairs, kSortTile));
   Control* ctl = at<Control>(b.ws, b.L.ctl);
   const uint32_t P = sp.passes;
@@ -464,13 +504,18 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
     a.shift = sp.shift[p];
     a.width = sp.width[p];
     a.counter = kCtrSort0 + p;
-    a.run = at<GridRun>(b.ws, b.L.run);
+    a.sink = at<GridSink>(b.ws, b.L.sink);
+    a.kmap = at<uint2>(b.ws, b.L.kmap);
+    {
+      const uint32_t kbits = bits_for(b.batch_cells);
+      a.kshift = kbits > static_cast<uint32_t>(kKeyMapBits) ? kbits - kKeyMapBits : 0;
+    }
     a.ctl = ctl;
     const bool regen = fused && p == 0;
     const bool shaped = !regen && !(B && last);
     const uint32_t pass_tiles =
         static_cast<uint32_t>(ceil_div(npairs, shaped ? sort_shape_tile(g_sort_shape) : kSortTile));
-    TraceScope ts(b.s, regen ? "onesweep_expand" : "onesweep");
+    TraceScope ts(b.s, regen ? "onesweep_expand" : (B && last) ? "onesweep_grids" : "onesweep");
     int st = launch_pass<B>(a, pass_bits(sp.width[p]), regen, B && last, pass_tiles, b.s);
     if (st) return st;
     GB_LAUNCHED();
@@ -662,9 +707,13 @@ namespace {
 
 struct BatchSetup {
   std::vector<GridDev> table;
-  uint64_t ntris = 0, cap = 0, cells = 0;
-  uint32_t cell_bits = 0, grid_bits = 0;
+  uint64_t ntris = 0, cap = 0, cells = 0;  // cells: the batch's cell space (sum of the grids' cells)
 };
+
+// Sort keys of a batch number the cells of all its grids in one space (each
+// grid's cells follow the previous grid's), so a batch fits when its total
+// cell count does not exceed 2^32.
+constexpr uint64_t kMaxBatchCells = uint64_t{1} << 32;
 
 int setup_batch(const grid_desc* grids, uint32_t ngrids, BatchSetup* bs, bool need_out) {
   if (!grids || ngrids == 0) return GRID_E_INVAL;
@@ -686,20 +735,19 @@ int setup_batch(const grid_desc* grids, uint32_t ngrids, BatchSetup* bs, bool ne
     bs->ntris += d.ntris;
     bs->cap += d.out.cap_pairs;
     bs->cells += ncells_of(d.res);
-    bs->cell_bits = std::max(bs->cell_bits, bits_for(ncells_of(d.res)));
   }
   if (bs->ntris >= (1u << 31)) return GRID_E_INVAL;
-  bs->grid_bits = bits_for(ngrids);
   return GRID_OK;
 }
 
-// Largest run of grids starting at g0 whose packed keys fit in 32 bits.
+// Largest run of grids starting at g0 whose cells fit in one 32-bit key space.
 uint32_t batch_chunk(const grid_desc* grids, uint32_t ngrids, uint32_t g0) {
-  uint32_t cb = 0, n = 0;
+  uint64_t cells = 0;
+  uint32_t n = 0;
   while (g0 + n < ngrids) {
-    const uint32_t cb2 = std::max(cb, bits_for(ncells_of(grids[g0 + n].res)));
-    if (cb2 + bits_for(n + 1) > 32) break;
-    cb = cb2;
+    const uint64_t c = cells + ncells_of(grids[g0 + n].res);
+    if (c > kMaxBatchCells) break;
+    cells = c;
     ++n;
   }
   return std::max(n, 1u);
@@ -709,19 +757,19 @@ int prepare_batched(Build& b, BatchSetup& bs, const grid_desc* grids, uint32_t n
                     hipStream_t s, bool need_out, void* staging = nullptr, size_t staging_bytes = 0) {
   int st = setup_batch(grids, ngrids, &bs, need_out);
   if (st) return st;
-  if (bs.cell_bits + bs.grid_bits > 32) return GRID_E_INVAL;
+  if (bs.cells > kMaxBatchCells) return GRID_E_INVAL;
   b.ws = ws;
   b.s = s;
   b.ntris = static_cast<uint32_t>(bs.ntris);
   b.batched = true;
-  b.plan = make_plan(std::max(1u, bs.cell_bits + bs.grid_bits));
+  b.plan = make_plan(std::max(1u, bits_for(bs.cells)));
+  b.batch_cells = bs.cells;
   b.L = make_layout(bs.ntris, bs.cap, bs.cells + ngrids, b.plan, ngrids, true);
   if (!ws) return GRID_E_INVAL;
   if (ws_bytes < b.L.total) return GRID_E_NOMEM;
   b.gs = GridSet{};
   b.gs.table = at<GridDev>(ws, b.L.table);
   b.gs.ngrids = ngrids;
-  b.gs.cell_bits = bs.cell_bits;
   if (staging) {
     // caller-owned pinned memory: the copy stays asynchronous
     if (staging_bytes < ngrids * sizeof(GridDev)) return GRID_E_NOMEM;
@@ -751,7 +799,7 @@ int count_phase_batched(Build& b, uint32_t ngrids, std::vector<uint64_t>& npairs
 size_t batched_ws_one(const grid_desc* grids, uint32_t ngrids, bool need_out) {
   BatchSetup bs;
   if (setup_batch(grids, ngrids, &bs, need_out)) return 0;
-  return make_layout(bs.ntris, bs.cap, bs.cells + ngrids, make_plan(std::max(1u, bs.cell_bits + bs.grid_bits)), ngrids,
+  return make_layout(bs.ntris, bs.cap, bs.cells + ngrids, make_plan(std::max(1u, bits_for(bs.cells))), ngrids,
                      true).total;
 }
 

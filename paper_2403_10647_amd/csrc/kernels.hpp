@@ -21,8 +21,7 @@ enum CounterSlot : uint32_t {
 struct GridSet {
   GridDev one;              // plain builds
   const GridDev* table;     // batched builds (device)
-  uint32_t ngrids;
-  uint32_t cell_bits;       // batched: key = (grid << cell_bits) | cell
+  uint32_t ngrids;          // batched: sort key = the grid's cell_base + its local cell id
 };
 
 template <bool Batched>
@@ -65,6 +64,7 @@ struct CountArgs {
   uint32_t* start;          // [ntris] exclusive pair offsets (global)
   uint64_t* box;            // [ntris] packed cell boxes
   uint32_t* tfo;            // [ntfo] owner of the first pair of each sort tile
+  uint32_t* tfg;            // [ntfo] batched: grid of that owner
   uint32_t ntfo;
   uint32_t sort_tile_shift; // log2 of the sort tile size
   uint64_t* status;         // [count tiles] look-back words
@@ -169,7 +169,13 @@ __global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
       // sort tiles whose first pair this object owns
       uint64_t j = (excl + tmask) >> a.sort_tile_shift;
       const uint64_t jlast = (excl + mine[k] - 1) >> a.sort_tile_shift;
-      for (; j <= jlast && j < a.ntfo; ++j) a.tfo[j] = static_cast<uint32_t>(t);
+      if (j <= jlast && j < a.ntfo) {
+        const uint32_t g = grid_search<Batched>(a.gs, static_cast<uint32_t>(t));  // rare: about one object per tile
+        for (; j <= jlast && j < a.ntfo; ++j) {
+          a.tfo[j] = static_cast<uint32_t>(t);
+          if constexpr (Batched) a.tfg[j] = g;
+        }
+      }
     }
     excl += mine[k];
   }
@@ -198,8 +204,63 @@ struct ExpandArgs {
   const uint32_t* start;    // [ntris] global pair offsets
   const uint64_t* box;      // [ntris]
   const uint32_t* tfo;      // [ntiles + ...] owner of each tile's first pair
+  const uint32_t* tfg;      // batched: grid of that owner
   uint32_t ntris;           // total triangles
 };
+
+// What the expansion needs of a triangle's grid to form its keys and values.
+struct GridKeyParams {
+  uint32_t res0, res01, cell_base, tri_base;
+};
+
+GB_DEV GridKeyParams key_params(const GridDev& G) {
+  return {G.res[0], G.res[0] * G.res[1], static_cast<uint32_t>(G.cell_base), G.tri_base};
+}
+
+// The grids of a tile's objects lie in [lo, hi] (batched); most tiles lie in
+// one grid, whose parameters are then loaded once for the whole tile.  A
+// thread visits its objects in increasing order, so in a tile that straddles
+// grids it keeps the parameters of its current grid and the first triangle of
+// the next one, and searches again only when an object crosses that boundary.
+struct TileGrids {
+  uint32_t lo, hi, cur, next_tb;
+  GridKeyParams p, q;
+};
+
+template <bool Batched>
+GB_DEV TileGrids tile_grids(const ExpandArgs& a, uint32_t tile, uint32_t ntiles) {
+  TileGrids t{};
+  if constexpr (Batched) {
+    // the tile is the same for the whole workgroup: made visibly uniform, the
+    // grid range and the parameters are scalar loads held in scalar registers
+    const uint32_t tu = __builtin_amdgcn_readfirstlane(tile);
+    t.lo = __builtin_amdgcn_readfirstlane(a.tfg[tu]);
+    t.hi = __builtin_amdgcn_readfirstlane(tu + 1 < ntiles ? a.tfg[tu + 1] : a.gs.ngrids - 1);
+    t.cur = t.lo;
+    t.p = key_params(a.gs.table[t.lo]);
+    t.q = t.p;
+    t.next_tb = t.lo + 1 < a.gs.ngrids ? a.gs.table[t.lo + 1].tri_base : 0xFFFFFFFFu;
+  } else {
+    t.p = key_params(a.gs.one);
+  }
+  return t;
+}
+
+// Parameters of object obj's grid (objects of a thread come in increasing order).
+template <bool Batched>
+GB_DEV GridKeyParams obj_params(const ExpandArgs& a, TileGrids& t, uint32_t obj) {
+  if constexpr (Batched) {
+    if (t.lo != t.hi) {
+      if (obj >= t.next_tb) {
+        t.cur = grid_of_tri<true>(a.gs, obj, t.cur);
+        t.q = key_params(a.gs.table[t.cur]);
+        t.next_tb = t.cur + 1 < a.gs.ngrids ? a.gs.table[t.cur + 1].tri_base : 0xFFFFFFFFu;
+      }
+      return t.q;
+    }
+  }
+  return t.p;
+}
 
 // Layout of the items a thread holds after expand_tile: wave-striped (item k
 // of lane l in wave w is slot w * 64 * K + k * 64 + l; what the radix rank
@@ -213,7 +274,8 @@ GB_DEV uint32_t item_slot(uint32_t tid, int k) {
 }
 
 // s_slot must hold padded(Block * K) words.  Returns the tile's item count.
-template <int Block, int K, bool Batched, int Layout = kStriped>
+// OneGrid: the caller guarantees that the tile's objects lie in one grid.
+template <int Block, int K, bool Batched, int Layout = kStriped, bool OneGrid = false>
 GB_DEV uint32_t expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs, uint32_t ntiles, uint32_t* s_slot,
                             uint32_t* s_wtot, uint32_t (&keys)[K], uint32_t (&vals)[K]) {
   constexpr int N = Block * K;
@@ -266,9 +328,11 @@ GB_DEV uint32_t expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs,
     for (int k = 0; k < K; ++k) s_slot[pad32(tid * K + k)] = sv[k];
     __syncthreads();
   }
-  uint32_t gcur = 0;
-  if constexpr (Batched) gcur = grid_search<true>(a.gs, t0);
-  if constexpr (Layout == kBlocked) {
+  TileGrids tg = tile_grids<Batched>(a, tile, ntiles);
+  // blocked tiles inside one grid step GlobalCoords; blocked tiles that
+  // straddle grids (rare) take the chunked path below, which keeps fewer
+  // registers live while it looks grids up
+  if (Layout == kBlocked && (!Batched || OneGrid || tg.lo == tg.hi)) {
     // A thread's K consecutive slots mostly belong to one object, and an owner
     // that starts inside the run starts at offset 0, so GlobalCoords is only
     // evaluated for the run's first slot and then stepped (x fastest) instead
@@ -306,12 +370,11 @@ GB_DEV uint32_t expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs,
           z += cy ? 1u : 0u;
         }
       }
-      const uint32_t g = grid_of_tri<Batched>(a.gs, obj, gcur);
-      const GridDev& G = grid_at<Batched>(a.gs, g);
-      const uint32_t cell = (b.lo[0] + x) + G.res[0] * (b.lo[1] + y) + G.res[0] * G.res[1] * (b.lo[2] + z);
+      const GridKeyParams& gp = tg.p;
+      const uint32_t cell = (b.lo[0] + x) + gp.res0 * (b.lo[1] + y) + gp.res01 * (b.lo[2] + z);
       if constexpr (Batched) {
-        keys[k] = (g << a.gs.cell_bits) | cell;
-        vals[k] = obj - G.tri_base;
+        keys[k] = gp.cell_base + cell;
+        vals[k] = obj - gp.tri_base;
       } else {
         keys[k] = cell;
         vals[k] = obj;
@@ -348,12 +411,11 @@ GB_DEV uint32_t expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs,
       const int k = c0 + c;
       const uint32_t idx = item_slot<Block, K, Layout>(tid, k);
       const Box b = unpack_box(bx[c]);
-      const uint32_t g = grid_of_tri<Batched>(a.gs, obj[c], gcur);
-      const GridDev& G = grid_at<Batched>(a.gs, g);
-      const uint32_t cell = cell_of(b, rid[c], G.res[0], G.res[0] * G.res[1]);
+      const GridKeyParams gp = obj_params<Batched>(a, tg, obj[c]);
+      const uint32_t cell = cell_of(b, rid[c], gp.res0, gp.res01);
       if constexpr (Batched) {
-        keys[k] = (g << a.gs.cell_bits) | cell;
-        vals[k] = obj[c] - G.tri_base;
+        keys[k] = gp.cell_base + cell;
+        vals[k] = obj[c] - gp.tri_base;
       } else {
         keys[k] = cell;
         vals[k] = obj[c];
@@ -396,6 +458,76 @@ struct ExpandOutArgs {
   Control* ctl;
 };
 
+// Batched tile whose objects lie in more than one grid.
+GB_DEV bool tile_straddles(const ExpandArgs& a, uint32_t tile, uint32_t ntiles) {
+  const uint32_t hi = tile + 1 < ntiles ? a.tfg[tile + 1] : a.gs.ngrids - 1;
+  return a.tfg[tile] != hi;
+}
+
+// Store a tile's pairs (a thread's K consecutive pairs, 16-byte stores when
+// all are present) and add its digits to the block's histograms.
+template <int Block, int K, int RB>
+GB_DEV void store_tile(const ExpandOutArgs& a, uint32_t tile, uint32_t n, const uint32_t (&keys)[K],
+                       const uint32_t (&vals)[K], uint32_t* s_hist) {
+  constexpr int N = Block * K;
+  constexpr int R = RB > 0 ? 1 << RB : 1;
+  const uint64_t base = static_cast<uint64_t>(tile) * N;
+  const uint32_t first = threadIdx.x * K;
+  if (a.vec16 && first + K <= n) {
+    uint4* ck = reinterpret_cast<uint4*>(a.cells + base + first);
+    uint4* ov = reinterpret_cast<uint4*>(a.objs + base + first);
+#pragma unroll
+    for (int q = 0; q < K / 4; ++q) {
+      ck[q] = make_uint4(keys[4 * q], keys[4 * q + 1], keys[4 * q + 2], keys[4 * q + 3]);
+      ov[q] = make_uint4(vals[4 * q], vals[4 * q + 1], vals[4 * q + 2], vals[4 * q + 3]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (first + k < n) {
+        a.cells[base + first + k] = keys[k];
+        a.objs[base + first + k] = vals[k];
+      }
+    }
+  }
+  if constexpr (RB > 0) {
+    // digit histograms: consecutive pairs of one object mostly share their
+    // upper digits, so each run of equal digits is added once
+    const uint32_t m = first < n ? (n - first < K ? n - first : K) : 0;
+    for (uint32_t p = 0; p < a.plan.passes; ++p) {
+      const uint32_t sh = a.plan.shift[p], dm = (1u << a.plan.width[p]) - 1u;
+      uint32_t cur = 0, cnt = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (static_cast<uint32_t>(k) < m) {
+          const uint32_t d = (keys[k] >> sh) & dm;
+          if (cnt != 0 && d != cur) {
+            atomicAdd(&s_hist[p * R + cur], cnt);
+            cnt = 0;
+          }
+          cur = d;
+          ++cnt;
+        }
+      }
+      if (cnt != 0) atomicAdd(&s_hist[p * R + cur], cnt);
+    }
+  }
+}
+
+template <int RB, int Block>
+GB_DEV void flush_hist(const ExpandOutArgs& a, const uint32_t* s_hist) {
+  constexpr int R = 1 << RB;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < a.plan.passes * R; i += Block) {
+    const uint32_t v = s_hist[i];
+    if (v) atomicAdd(&a.hist[(i / R) * kRadixMax + (i % R)], v);
+  }
+}
+
+// The expansion written out in object order, with the digit histograms of
+// every radix pass and the look-back words of every pass cleared.  Batched
+// builds skip the tiles that straddle grids here; expand_straddle_kernel
+// writes those.
 template <int Block, int K, int RB, bool Batched>
 __global__ __launch_bounds__(Block, 4) void expand_kernel(ExpandOutArgs a) {
   constexpr int N = Block * K;
@@ -419,58 +551,41 @@ __global__ __launch_bounds__(Block, 4) void expand_kernel(ExpandOutArgs a) {
   while (true) {
     const uint32_t tile = next_tile(&a.ctl->tile_counter[kCtrExpand], &s_tile);
     if (tile >= ntiles) break;
+    if constexpr (Batched) {
+      if (tile_straddles(a.ex, __builtin_amdgcn_readfirstlane(tile), ntiles)) continue;
+    }
     uint32_t keys[K], vals[K];
-    const uint32_t n = expand_tile<Block, K, Batched, kBlocked>(a.ex, tile, npairs, ntiles, s_owner, s_wtot, keys, vals);
-    const uint64_t base = static_cast<uint64_t>(tile) * N;
-    const uint32_t first = threadIdx.x * K;
-    // this thread's K consecutive pairs: 16-byte stores when all are present
-    if (a.vec16 && first + K <= n) {
-      uint4* ck = reinterpret_cast<uint4*>(a.cells + base + first);
-      uint4* ov = reinterpret_cast<uint4*>(a.objs + base + first);
-#pragma unroll
-      for (int q = 0; q < K / 4; ++q) {
-        ck[q] = make_uint4(keys[4 * q], keys[4 * q + 1], keys[4 * q + 2], keys[4 * q + 3]);
-        ov[q] = make_uint4(vals[4 * q], vals[4 * q + 1], vals[4 * q + 2], vals[4 * q + 3]);
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        if (first + k < n) {
-          a.cells[base + first + k] = keys[k];
-          a.objs[base + first + k] = vals[k];
-        }
-      }
-    }
-    if constexpr (RB > 0) {
-      // digit histograms: consecutive pairs of one object mostly share their
-      // upper digits, so each run of equal digits is added once
-      const uint32_t m = first < n ? (n - first < K ? n - first : K) : 0;
-      for (uint32_t p = 0; p < a.plan.passes; ++p) {
-        const uint32_t sh = a.plan.shift[p], dm = (1u << a.plan.width[p]) - 1u;
-        uint32_t cur = 0, cnt = 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          if (static_cast<uint32_t>(k) < m) {
-            const uint32_t d = (keys[k] >> sh) & dm;
-            if (cnt != 0 && d != cur) {
-              atomicAdd(&s_hist[p * R + cur], cnt);
-              cnt = 0;
-            }
-            cur = d;
-            ++cnt;
-          }
-        }
-        if (cnt != 0) atomicAdd(&s_hist[p * R + cur], cnt);
-      }
-    }
+    const uint32_t n =
+        expand_tile<Block, K, Batched, kBlocked, true>(a.ex, tile, npairs, ntiles, s_owner, s_wtot, keys, vals);
+    store_tile<Block, K, RB>(a, tile, n, keys, vals, s_hist);
   }
+  if constexpr (RB > 0) flush_hist<RB, Block>(a, s_hist);
+}
+
+// Batched builds: the tiles whose objects lie in more than one grid (about
+// one per grid boundary), with the grid looked up per object.
+template <int Block, int K, int RB>
+__global__ __launch_bounds__(Block, 2) void expand_straddle_kernel(ExpandOutArgs a) {
+  constexpr int N = Block * K;
+  constexpr int R = RB > 0 ? 1 << RB : 1;
+  __shared__ uint32_t s_owner[padded(N)];
+  __shared__ uint32_t s_hist[RB > 0 ? 4 * R : 1];
+  __shared__ uint32_t s_wtot[Block / kWave];
+  if (build_failed(a.ctl)) return;
+  const uint64_t npairs = a.ctl->npairs;
+  const uint32_t ntiles = static_cast<uint32_t>((npairs + N - 1) / N);
   if constexpr (RB > 0) {
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < a.plan.passes * R; i += Block) {
-      const uint32_t v = s_hist[i];
-      if (v) atomicAdd(&a.hist[(i / R) * kRadixMax + (i % R)], v);
-    }
+    for (int i = threadIdx.x; i < 4 * R; i += Block) s_hist[i] = 0;
   }
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    if (!tile_straddles(a.ex, __builtin_amdgcn_readfirstlane(tile), ntiles)) continue;
+    __syncthreads();  // the previous tile's readers of s_owner are done
+    uint32_t keys[K], vals[K];
+    const uint32_t n =
+        expand_tile<Block, K, true, kBlocked, false>(a.ex, tile, npairs, ntiles, s_owner, s_wtot, keys, vals);
+    store_tile<Block, K, RB>(a, tile, n, keys, vals, s_hist);
+  }
+  if constexpr (RB > 0) flush_hist<RB, Block>(a, s_hist);
 }
 
 // One read of the keys (regenerated from the expansion) for the digit

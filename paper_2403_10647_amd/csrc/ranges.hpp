@@ -70,6 +70,72 @@ __global__ __launch_bounds__(Block) void plan_kernel(PlanArgs a) {
   if (threadIdx.x == 0) a.run[G].mtile_base = carry;
 }
 
+// Where the last radix pass of a batched build writes each grid's pairs: its
+// output arrays, its first pair in the batch and its first cell in the batch's
+// cell space (32 bytes, read with two vector loads).
+struct alignas(16) GridSink {
+  uint32_t* cells;
+  uint32_t* objs;
+  uint64_t pair_base;
+  uint32_t cell_base;
+  uint32_t pad;
+};
+
+// Sort keys number the cells of all grids of a batch in one space.  Bucket j
+// of the key map covers the keys [j << kshift, (j + 1) << kshift) and holds the
+// grids of its first and last key, so the grid of a key is one cached load
+// away, with a short search only in the few buckets a grid boundary crosses.
+struct SinkArgs {
+  GridSet gs;
+  const GridRun* run;
+  GridSink* sink;          // [ngrids]
+  uint2* kmap;             // [nbuckets]
+  uint32_t nbuckets;
+  uint32_t kshift;
+  uint64_t ncells;         // cells of the batch: every key is below it
+};
+
+// Largest g with cell_base[g] <= key.
+GB_DEV uint32_t grid_of_cell(const GridSet& s, uint64_t key) {
+  uint32_t lo = 0, hi = s.ngrids;  // answer in [lo, hi)
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (s.table[mid].cell_base <= key) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <int Block>
+__global__ __launch_bounds__(Block) void sink_kernel(SinkArgs a) {
+  const uint32_t stride = gridDim.x * Block;
+  const uint32_t first = blockIdx.x * Block + threadIdx.x;
+  for (uint32_t g = first; g < a.gs.ngrids; g += stride) {
+    const GridDev& d = a.gs.table[g];
+    GridSink k;
+    k.cells = d.out_cells;
+    k.objs = d.out_objs;
+    k.pair_base = a.run[g].pair_base;
+    k.cell_base = static_cast<uint32_t>(d.cell_base);
+    k.pad = 0;
+    a.sink[g] = k;
+  }
+  for (uint32_t j = first; j < a.nbuckets; j += stride) {
+    const uint64_t k0 = static_cast<uint64_t>(j) << a.kshift;
+    const uint64_t k1e = (static_cast<uint64_t>(j + 1) << a.kshift) - 1;
+    const uint64_t k1 = k1e < a.ncells - 1 ? k1e : a.ncells - 1;
+    a.kmap[j] = make_uint2(grid_of_cell(a.gs, k0), grid_of_cell(a.gs, k1));
+  }
+}
+
+// Grid of key within [lo, hi] (binary search over the sinks, one thread).
+GB_DEV uint32_t sink_of_key(const GridSink* sink, uint32_t key, uint32_t lo, uint32_t hi) {
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (sink[mid].cell_base <= key) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Grid of merge tile b: largest g with run[g].mtile_base <= b.
 GB_DEV uint32_t grid_of_mtile(const GridRun* run, uint32_t ngrids, uint32_t b) {
   uint32_t lo = 0, hi = ngrids;

@@ -25,7 +25,9 @@ struct SortPassArgs {
   uint32_t shift;
   uint32_t width;           // digit width of this pass (<= RB)
   uint32_t counter;         // tile-counter slot
-  const GridRun* run;       // kToGrids: each grid's first pair
+  const GridSink* sink;     // kToGrids: each grid's outputs, first pair and first cell
+  const uint2* kmap;        // kToGrids: key bucket -> (first, last) grid
+  uint32_t kshift;          // kToGrids: key bucket = key >> kshift
   Control* ctl;
 };
 
@@ -219,11 +221,12 @@ __global__ __launch_bounds__(Block, Source == kFromArrays ? 4 : 2) void onesweep
         a.keys_out[dst] = key;
         a.vals_out[dst] = val;
       } else {
-        const uint32_t g = key >> a.ex.gs.cell_bits;
-        const GridDev& G = a.ex.gs.table[g];
-        const uint64_t local = dst - a.run[g].pair_base;
-        G.out_cells[local] = key & ((1u << a.ex.gs.cell_bits) - 1u);
-        G.out_objs[local] = val;
+        const uint2 km = a.kmap[key >> a.kshift];
+        const uint32_t g = km.x == km.y ? km.x : sink_of_key(a.sink, key, km.x, km.y);
+        const GridSink k = a.sink[g];
+        const uint64_t local = dst - k.pair_base;
+        k.cells[local] = key - k.cell_base;
+        k.objs[local] = val;
       }
     }
     __syncthreads();

@@ -18,8 +18,8 @@ scene (its stand-alone build); mismatches are counted per slot and read back
 once at the end, off the timed path.
 
 Batch formation (``form_batch``) is pure host logic: FIFO order, a cap on
-grids and pairs per batch, packed (grid, cell) keys within 32 bits, and the
-byte budget.
+grids and pairs per batch, the batch's cells within one 32-bit key space, and
+the byte budget.
 """
 from __future__ import annotations
 
@@ -32,6 +32,9 @@ import numpy as np
 import torch
 
 from . import _lib as G
+
+
+MAX_BATCH_CELLS = 1 << 32   # a batch numbers its grids' cells in one 32-bit key space
 
 
 def bits_for(n: int) -> int:
@@ -50,10 +53,6 @@ class Request:
     done: float = -1.0
     status: int = 0                # GRID_OK, or why the request failed / was rejected
     result: Optional[G.GridResult] = None
-
-    @property
-    def cell_bits(self) -> int:
-        return bits_for(self.inp.ncells)
 
     @property
     def latency(self) -> float:
@@ -77,18 +76,17 @@ def form_batch(queue: Sequence[Request], free_bytes: int, max_grids: int, max_pa
     """How many requests from the head of the FIFO queue go into the next batch.
 
     The batch grows while the next request's outputs fit in free_bytes, the
-    packed (grid, cell) keys still fit in 32 bits, the batch holds at most
-    max_grids grids and, unless it is empty, at most max_pairs pairs.  Returns 0
-    when the head itself does not fit in free_bytes."""
+    batch's cells (all grids numbered in one space) still fit 32-bit sort keys,
+    the batch holds at most max_grids grids and, unless it is empty, at most
+    max_pairs pairs.  Returns 0 when the head itself does not fit in free_bytes."""
     n = 0
     used = 0
     pairs = 0
-    cbits = 0
+    cells = 0
     for r in queue:
         if n >= max_grids:
             break
-        cb = max(cbits, r.cell_bits)
-        if cb + bits_for(n + 1) > 32:
+        if cells + r.inp.ncells > MAX_BATCH_CELLS:
             break
         if n > 0 and pairs + r.npairs > max_pairs:
             break
@@ -97,7 +95,7 @@ def form_batch(queue: Sequence[Request], free_bytes: int, max_grids: int, max_pa
         n += 1
         used += r.out_bytes
         pairs += r.npairs
-        cbits = cb
+        cells += r.inp.ncells
     return n
 
 

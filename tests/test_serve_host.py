@@ -45,14 +45,13 @@ def test_form_batch_head_may_exceed_pair_cap():
 
 
 def test_form_batch_keeps_keys_within_32_bits():
-    # 2^27-cell grids: 27 cell bits leave 5 grid bits, so at most 32 such grids
+    # the cells of a batch's grids are numbered in one 32-bit space
     q = [_req(i, 1, 1 << 27) for i in range(40)]
     assert serve.form_batch(q, 1 << 50, 512, 1 << 30) == 32
-    q = [_req(i, 1, 1 << 30) for i in range(5)]          # 30 cell bits: four grids (2 grid bits)
+    q = [_req(i, 1, 1 << 30) for i in range(5)]
     assert serve.form_batch(q, 1 << 50, 512, 1 << 30) == 4
-    # a wide grid arriving later stops the batch before it
-    q = [_req(i, 1, 1 << 10) for i in range(100)] + [_req(100, 1, 1 << 30)]
-    assert serve.form_batch(q, 1 << 50, 512, 1 << 30) == 100
+    q = [_req(i, 1, 1 << 10) for i in range(100)] + [_req(100, 1, 1 << 30)] * 4
+    assert serve.form_batch(q, 1 << 50, 512, 1 << 30) == 103   # 100 * 2^10 + 3 * 2^30 < 2^32
 
 
 def test_poisson_arrivals():
