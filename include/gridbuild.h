@@ -100,9 +100,11 @@ int grid_count(const float *verts_soa, uint32_t nverts, const uint32_t *tris, ui
                void *ws, size_t ws_bytes, uint32_t *start_out, uint64_t *npairs, void *stream);
 
 /* The whole build, BuildParallelGrid(M, boxes) -> (G, O) (Algorithm 1), into
- * out (cells, objs: cap_pairs entries; ranges: 2 * R entries).  Synchronizes
- * stream once, after the count, to size the pair list (the paper allocates O and
- * C from NO at that point); the rest is left ordered on stream. */
+ * out (cells, objs: cap_pairs entries; ranges: 2 * R entries).  Every kernel
+ * after the count reads NO from device memory and stops before writing if it
+ * exceeds cap_pairs, so the whole sequence is launched at once and stream is
+ * synchronized once, at the end, to read NO back into out->npairs (also on
+ * GRID_E_CAPACITY, which leaves the outputs untouched). */
 int grid_build(const float *verts_soa, uint32_t nverts, const uint32_t *tris, uint32_t ntris,
                const float lo[3], const float hi[3], const uint32_t res[3],
                void *ws, size_t ws_bytes, grid_out *out, void *stream);
@@ -209,6 +211,12 @@ typedef struct grid_trace_entry {
 /* Turn tracing on (1) or off (0) for the whole process.  While on, each kernel
  * launch is bracketed by HIP events recorded on the launch's own stream. */
 int grid_trace_enable(int on);
+
+/* Restrict tracing to the launches of one kernel (a name as reported by
+ * grid_trace_read, at most 47 characters), or trace every kernel again when
+ * name is NULL.  Fewer events keep the traced run closer to an untraced one.
+ * GRID_E_INVAL for an empty or too long name. */
+int grid_trace_only(const char *name);
 
 /* Wait for the traced launches, fold them into per-kernel totals and reset.
  * Writes up to max_entries entries (host array) and *n_entries (host) = the

@@ -35,7 +35,7 @@ EXPORTS = (
     "grid_workspace_size_batched", "grid_count_batched", "grid_build_batched",
     "grid_sort_workspace_size", "grid_sort_pairs", "grid_scan_workspace_size", "grid_scan_u32",
     "grid_trace_enable", "grid_trace_read", "grid_tune_set", "grid_tune_get", "grid_sort_plan",
-    "grid_batch_staging_size", "grid_build_batched_async", "grid_workspace_status",
+    "grid_batch_staging_size", "grid_build_batched_async", "grid_workspace_status", "grid_trace_only",
 )
 
 
@@ -107,6 +107,8 @@ def lib():
         L.grid_sort_plan.restype = C.c_int
         L.grid_tune_get.restype = C.c_int
         L.grid_trace_enable.argtypes = [C.c_int]
+        L.grid_trace_only.argtypes = [C.c_char_p]
+        L.grid_trace_only.restype = C.c_int
         L.grid_trace_read.argtypes = [C.POINTER(grid_trace_entry), C.c_int, C.POINTER(C.c_int)]
         for name in ("grid_trace_enable", "grid_trace_read", "grid_count", "grid_build", "grid_expand", "grid_count_batched", "grid_build_batched",
                      "grid_sort_pairs", "grid_scan_u32"):
@@ -348,6 +350,11 @@ def scan_u32(x: torch.Tensor, op: int, flags: Optional[torch.Tensor] = None, ws:
 
 def trace_enable(on: bool = True):
     _check(lib().grid_trace_enable(1 if on else 0), "grid_trace_enable")
+
+
+def trace_only(name: Optional[str]):
+    """Trace only the launches of kernel ``name`` (None: every kernel)."""
+    _check(lib().grid_trace_only(name.encode() if name is not None else None), "grid_trace_only")
 
 
 def trace_read() -> dict:

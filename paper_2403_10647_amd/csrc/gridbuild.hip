@@ -73,6 +73,7 @@ struct TraceRec {
 struct Tracer {
   std::mutex mu;
   bool on = false;
+  char only[48] = {0};  // when set, only launches of this kernel are traced
   std::vector<TraceRec> recs;
   std::vector<hipEvent_t> pool;
   hipEvent_t get() {
@@ -97,6 +98,7 @@ class TraceScope {
     Tracer& t = tracer();
     if (!t.on) return;
     std::lock_guard<std::mutex> lock(t.mu);
+    if (t.only[0] && std::strncmp(t.only, name, sizeof(t.only)) != 0) return;
     rec_.name = name;
     rec_.a = t.get();
     rec_.b = t.get();
@@ -369,36 +371,35 @@ int launch_expand(Build& b, uint32_t* cells, uint32_t* objs, uint64_t npairs) {
 // 8-bit pass of a 25-bit key does not pay for 9-bit ranking.
 int pass_bits(uint32_t width) { return std::max(8, static_cast<int>(width)); }
 
+template <int Blk, int K, int RB, int Src, int Snk, bool B>
+void launch_onesweep(const SortPassArgs& a, uint32_t ntiles, hipStream_t s) {
+  auto k = onesweep_kernel<Blk, K, RB, Src, Snk, B>;
+  k<<<resident_blocks(k, Blk, ntiles), Blk, 0, s>>>(a);
+}
+
+// A pass that reads arrays runs in the tile shape the sort_shape knob picks.
+template <int RB, int Snk, bool B>
+void launch_shaped(const SortPassArgs& a, uint32_t ntiles, hipStream_t s) {
+  switch (g_sort_shape) {
+    case 1: launch_onesweep<256, 16, RB, kFromArrays, Snk, B>(a, ntiles, s); break;
+    case 2: launch_onesweep<1024, 8, RB, kFromArrays, Snk, B>(a, ntiles, s); break;
+    case 3: launch_onesweep<1024, 16, RB, kFromArrays, Snk, B>(a, ntiles, s); break;
+    case 4: launch_onesweep<1024, 15, RB, kFromArrays, Snk, B>(a, ntiles, s); break;
+    default: launch_onesweep<kSortBlock, kSortK, RB, kFromArrays, Snk, B>(a, ntiles, s); break;
+  }
+}
+
 template <int RB, bool B>
 int launch_pass_rb(const SortPassArgs& a, bool regen, bool to_grids, uint32_t ntiles, hipStream_t s) {
   if (regen) {
-    if (to_grids) {
-      auto k = onesweep_kernel<kSortBlock, kSortK, RB, kFromExpansion, kToGrids, B>;
-      k<<<resident_blocks(k, kSortBlock, ntiles), kSortBlock, 0, s>>>(a);
-    } else {
-      auto k = onesweep_kernel<kSortBlock, kSortK, RB, kFromExpansion, kToArrays, B>;
-      k<<<resident_blocks(k, kSortBlock, ntiles), kSortBlock, 0, s>>>(a);
-    }
+    // regenerating passes read the expansion, whose tiles are kSortTile pairs
+    if (to_grids) launch_onesweep<kSortBlock, kSortK, RB, kFromExpansion, kToGrids, B>(a, ntiles, s);
+    else launch_onesweep<kSortBlock, kSortK, RB, kFromExpansion, kToArrays, B>(a, ntiles, s);
+  } else if (to_grids) {
+    if constexpr (B) launch_shaped<RB, kToGrids, B>(a, ntiles, s);
+    else return GRID_E_INVAL;  // plain builds end in the caller's arrays
   } else {
-    if (to_grids) {
-      auto k = onesweep_kernel<kSortBlock, kSortK, RB, kFromArrays, kToGrids, B>;
-      k<<<resident_blocks(k, kSortBlock, ntiles), kSortBlock, 0, s>>>(a);
-    } else if (g_sort_shape == 1) {
-      auto k = onesweep_kernel<256, 16, RB, kFromArrays, kToArrays, B>;
-      k<<<resident_blocks(k, 256, ntiles), 256, 0, s>>>(a);
-    } else if (g_sort_shape == 2) {
-      auto k = onesweep_kernel<1024, 8, RB, kFromArrays, kToArrays, B>;
-      k<<<resident_blocks(k, 1024, ntiles), 1024, 0, s>>>(a);
-    } else if (g_sort_shape == 3) {
-      auto k = onesweep_kernel<1024, 16, RB, kFromArrays, kToArrays, B>;
-      k<<<resident_blocks(k, 1024, ntiles), 1024, 0, s>>>(a);
-    } else if (g_sort_shape == 4) {
-      auto k = onesweep_kernel<1024, 15, RB, kFromArrays, kToArrays, B>;
-      k<<<resident_blocks(k, 1024, ntiles), 1024, 0, s>>>(a);
-    } else {
-      auto k = onesweep_kernel<kSortBlock, kSortK, RB, kFromArrays, kToArrays, B>;
-      k<<<resident_blocks(k, kSortBlock, ntiles), kSortBlock, 0, s>>>(a);
-    }
+    launch_shaped<RB, kToArrays, B>(a, ntiles, s);
   }
   GB_LAUNCHED();
   return GRID_OK;
@@ -512,7 +513,7 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
     }
     a.ctl = ctl;
     const bool regen = fused && p == 0;
-    const bool shaped = !regen && !(B && last);
+    const bool shaped = !regen;
     const uint32_t pass_tiles =
         static_cast<uint32_t>(ceil_div(npairs, shaped ? sort_shape_tile(g_sort_shape) : kSortTile));
     TraceScope ts(b.s, regen ? "onesweep_expand" : (B && last) ? "onesweep_grids" : "onesweep");
@@ -666,18 +667,24 @@ int grid_build(const float* verts_soa, uint32_t nverts, const uint32_t* tris, ui
   b.gs.one.out_cells = out->cells;
   b.gs.one.out_objs = out->objs;
   b.gs.one.out_ranges = out->ranges;
-  HostCtl h{};
-  st = count_phase_plain(b, &h);
-  out->npairs = h.npairs;
-  if (st) return st;
-  if (h.npairs > out->cap_pairs) return GRID_E_CAPACITY;
+  // the capacity bounds every launch; the kernels read the real NO on the device
+  const uint64_t cap = out->cap_pairs;
+  if ((st = launch_zero(b.ws, b.L.zero_end, b.s))) return st;
+  if ((st = launch_count<false>(b))) return st;
   if ((st = launch_plan<false>(b))) return st;
   if (b.plan.sp.passes == 0) {
-    if ((st = launch_expand<0, false>(b, out->cells, out->objs, h.npairs))) return st;
-  } else if (h.npairs > 0) {
-    if ((st = launch_sort<false>(b, out->cells, out->objs, h.npairs))) return st;
+    if ((st = launch_expand<0, false>(b, out->cells, out->objs, cap))) return st;
+  } else if (cap > 0) {
+    if ((st = launch_sort<false>(b, out->cells, out->objs, cap))) return st;
   }
-  return launch_ranges<false>(b, ncells_of(res) + 1 + h.npairs);
+  if ((st = launch_ranges<false>(b, ncells_of(res) + 1 + cap))) return st;
+  HostCtl h{};
+  if ((st = read_ctl(b, &h))) return st;
+  out->npairs = h.npairs;
+  if (h.error & kErrBadIndex) return GRID_E_BADINDEX;
+  if (h.npairs > 0xFFFFFFFFull) return GRID_E_OVERFLOW;
+  if (h.npairs > cap) return GRID_E_CAPACITY;
+  return GRID_OK;
 }
 
 int grid_expand(const float* verts_soa, uint32_t nverts, const uint32_t* tris, uint32_t ntris, const float lo[3],
@@ -1027,6 +1034,19 @@ int grid_trace_enable(int on) {
   Tracer& t = tracer();
   std::lock_guard<std::mutex> lock(t.mu);
   t.on = on != 0;
+  return GRID_OK;
+}
+
+int grid_trace_only(const char* name) {
+  Tracer& t = tracer();
+  std::lock_guard<std::mutex> lock(t.mu);
+  if (!name) {
+    t.only[0] = 0;
+    return GRID_OK;
+  }
+  if (std::strlen(name) == 0 || std::strlen(name) >= sizeof(t.only)) return GRID_E_INVAL;
+  std::strncpy(t.only, name, sizeof(t.only) - 1);
+  t.only[sizeof(t.only) - 1] = 0;
   return GRID_OK;
 }
 

@@ -212,21 +212,46 @@ __global__ __launch_bounds__(Block, Source == kFromArrays ? 4 : 2) void onesweep
     __syncthreads();
 
     // ---- scatter: consecutive threads write consecutive slots of a digit run ----
-    for (uint32_t i = tid; i < nt; i += Block) {
-      const uint32_t key = s_stage[i];
-      const uint32_t val = s_stage[N + i];
-      const uint32_t d = (key >> a.shift) & dmask;
-      const uint32_t dst = s_dst[d] + i;
-      if constexpr (Sink == kToArrays) {
+    if constexpr (Sink == kToArrays) {
+      for (uint32_t i = tid; i < nt; i += Block) {
+        const uint32_t key = s_stage[i];
+        const uint32_t val = s_stage[N + i];
+        const uint32_t d = (key >> a.shift) & dmask;
+        const uint32_t dst = s_dst[d] + i;
         a.keys_out[dst] = key;
         a.vals_out[dst] = val;
-      } else {
-        const uint2 km = a.kmap[key >> a.kshift];
-        const uint32_t g = km.x == km.y ? km.x : sink_of_key(a.sink, key, km.x, km.y);
-        const GridSink k = a.sink[g];
-        const uint64_t local = dst - k.pair_base;
-        k.cells[local] = key - k.cell_base;
-        k.objs[local] = val;
+      }
+    } else {
+      // batched: each slot's grid comes from the key map and the grid's
+      // output descriptor; the lookups of C slots are in flight together
+      constexpr int C = 4;
+      for (uint32_t i0 = tid; i0 < nt; i0 += C * Block) {
+        uint32_t kk[C], vv[C];
+        uint2 km[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const uint32_t i = i0 + c * Block;
+          const uint32_t ii = i < nt ? i : nt - 1;  // past the tail: a valid slot, nothing stored
+          kk[c] = s_stage[ii];
+          vv[c] = s_stage[N + ii];
+          km[c] = a.kmap[kk[c] >> a.kshift];
+        }
+        GridSink sk[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const uint32_t g = km[c].x == km[c].y ? km[c].x : sink_of_key(a.sink, kk[c], km[c].x, km[c].y);
+          sk[c] = a.sink[g];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const uint32_t i = i0 + c * Block;
+          if (i < nt) {
+            const uint32_t dst = s_dst[(kk[c] >> a.shift) & dmask] + i;
+            const uint64_t local = dst - sk[c].pair_base;
+            sk[c].cells[local] = kk[c] - sk[c].cell_base;
+            sk[c].objs[local] = vv[c];
+          }
+        }
       }
     }
     __syncthreads();

@@ -132,6 +132,15 @@ def test_trace_read_without_launches(G):
     G.trace_enable(False)
 
 
+def test_trace_only_validates_names(G):
+    G.trace_only("onesweep")
+    G.trace_only(None)
+    with pytest.raises(G.GridError):
+        G.trace_only("")
+    with pytest.raises(G.GridError):
+        G.trace_only("x" * 48)
+
+
 @pytest.mark.parametrize("digit", [4, 5, 6, 7, 8, 9, 10, 11])
 def test_sort_plan_is_valid_for_every_width(G, digit):
     # regression: a narrow digit limit on a wide key once asked for more than

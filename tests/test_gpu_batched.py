@@ -126,10 +126,12 @@ def test_batched_chunks_when_keys_exceed_32_bits(G):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("fused,digit", [(0, 8), (1, 8), (1, 10), (0, 11)])
-def test_batched_under_tuning(G, fused, digit):
+@pytest.mark.parametrize("fused,digit,shape", [(0, 8, 3), (1, 8, 3), (1, 10, 3), (0, 11, 3), (0, 9, 0), (0, 9, 1),
+                                                (0, 9, 2), (0, 10, 4)])
+def test_batched_under_tuning(G, fused, digit, shape):
     G.tune_set("fused_expand", fused)
     G.tune_set("max_digit_bits", digit)
+    G.tune_set("sort_shape", shape)
     try:
         batch = _uneven_batch()[:9]
         res = G.build_batched([G.GridInput.from_scene(s) for s in batch])
@@ -138,3 +140,4 @@ def test_batched_under_tuning(G, fused, digit):
     finally:
         G.tune_set("fused_expand", 0)
         G.tune_set("max_digit_bits", 9)
+        G.tune_set("sort_shape", 3)

@@ -240,23 +240,55 @@ def test_error_paths(G):
         with pytest.raises(G.GridError) as e:
             G.build(bad, cap_pairs=10)
         assert e.value.status == G.GRID_E_INVAL
-    # capacity too small reports the required count
+    # capacity too small reports the required count and writes no output
     no, _ = G.count(g)
+
+    def sentinel_out(cap, ncells):
+        r = G.GridResult(torch.full((max(cap, 1),), -7, dtype=torch.int32, device="cuda"),
+                         torch.full((max(cap, 1),), -7, dtype=torch.int32, device="cuda"),
+                         torch.full((2 * ncells,), -7, dtype=torch.int32, device="cuda"), 0)
+        return r
+
+    out = sentinel_out(no - 1, g.ncells)
     with pytest.raises(G.GridError) as e:
-        G.build(g, cap_pairs=no - 1)
-    assert e.value.status == G.GRID_E_CAPACITY
+        G.build(g, out=out)
+    assert e.value.status == G.GRID_E_CAPACITY and out.npairs == no
+    assert bool((out.cells == -7).all()) and bool((out.objs == -7).all()) and bool((out.ranges == -7).all())
     # vertex index out of range (flagged by the count kernel)
     t = g.tris.clone()
     t[5, 1] = g.nverts + 3
+    out = sentinel_out(no, g.ncells)
     with pytest.raises(G.GridError) as e:
-        G.build(G.GridInput(g.verts, t, g.lo, g.hi, g.res), cap_pairs=no)
+        G.build(G.GridInput(g.verts, t, g.lo, g.hi, g.res), out=out)
     assert e.value.status == G.GRID_E_BADINDEX
+    assert bool((out.cells == -7).all()) and bool((out.ranges == -7).all())
     # NO beyond 2^32 - 1
     verts, tris = _soup([[[0, 0, 0], [1, 1, 1], [0, 1, 0]]] * 5)
     big = G.GridInput.from_scene(_scene(verts, tris, [0, 0, 0], [1, 1, 1], [1024, 1024, 1024]))
     with pytest.raises(G.GridError) as e:
         G.count(big)
     assert e.value.status == G.GRID_E_OVERFLOW
+    with pytest.raises(G.GridError) as e:
+        G.build(big, cap_pairs=1000)
+    assert e.value.status == G.GRID_E_OVERFLOW
+    # a workspace used by a failed build serves the next one
+    r = G.build(g, cap_pairs=no)
+    oc, oo, orr = oracle.build_scene(s)
+    c, o, rg = r.numpy()
+    assert np.array_equal(c, oc) and np.array_equal(o, oo) and np.array_equal(rg, orr)
+
+
+def test_build_with_spare_capacity(G):
+    # launches are sized by the capacity; the kernels use the NO they count
+    for name, n in [("small", 4096), ("mixed", 30_000)]:
+        s = scenes.make_scene(name, ntris=n)
+        g = G.GridInput.from_scene(s)
+        no, _ = G.count(g)
+        r = G.build(g, cap_pairs=3 * no + 100_000)
+        assert r.npairs == no
+        oc, oo, orr = oracle.build_scene(s)
+        c, o, rg = r.numpy()
+        assert np.array_equal(c, oc) and np.array_equal(o, oo) and np.array_equal(rg, orr)
 
 
 @pytest.mark.parametrize("fused", [0, 1])
