@@ -336,6 +336,29 @@ uint32_t resident_blocks(F kernel, int block, uint64_t tiles) {
   return persistent_blocks(tiles, per_cu);
 }
 
+int pass_bits(uint32_t width);
+
+// Tile size of radix pass p under the current knobs (a regenerating first pass
+// reads the expansion's tiles; the others take the sort_shape tile).
+uint32_t pass_tile(uint32_t p) {
+  return (g_fused_expand && p == 0) ? static_cast<uint32_t>(kSortTile)
+                                    : static_cast<uint32_t>(sort_shape_tile(g_sort_shape));
+}
+
+// The look-back words each radix pass of b's plan will use (kernels built for
+// RB-bit digits lay the passes out RB-wide).
+StatusClear status_clear(const Build& b, int RB) {
+  StatusClear c{};
+  c.status = at<uint64_t>(b.ws, b.L.sort_status);
+  c.stride = static_cast<uint64_t>(b.L.nsort_tiles_cap) * (RB > 0 ? (1u << RB) : 1u);
+  c.passes = RB > 0 ? b.plan.sp.passes : 0;
+  for (uint32_t p = 0; p < c.passes; ++p) {
+    c.tile[p] = pass_tile(p);
+    c.radix[p] = 1u << pass_bits(b.plan.sp.width[p]);
+  }
+  return c;
+}
+
 template <int RB, bool B>
 int launch_expand(Build& b, uint32_t* cells, uint32_t* objs, uint64_t npairs) {
   if (npairs == 0) return GRID_OK;
@@ -346,9 +369,7 @@ int launch_expand(Build& b, uint32_t* cells, uint32_t* objs, uint64_t npairs) {
   a.objs = objs;
   a.plan = b.plan.sp;
   a.hist = at<uint32_t>(b.ws, b.L.hist);
-  a.sort_status = at<uint64_t>(b.ws, b.L.sort_status);
-  a.status_stride = static_cast<uint64_t>(b.L.nsort_tiles_cap) * (RB > 0 ? (1u << RB) : 1u);
-  a.clear_tile = kSortTileMin;
+  a.clear = status_clear(b, RB);
   a.vec16 = ((reinterpret_cast<uintptr_t>(cells) | reinterpret_cast<uintptr_t>(objs)) & 15u) == 0;
   a.ctl = at<Control>(b.ws, b.L.ctl);
   {
@@ -473,9 +494,7 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
     h.ex = expand_args(b);
     h.plan = sp;
     h.hist = at<uint32_t>(b.ws, b.L.hist);
-    h.sort_status = at<uint64_t>(b.ws, b.L.sort_status);
-    h.status_stride = static_cast<uint64_t>(b.L.nsort_tiles_cap) * (1u << RB);
-    h.clear_tile = kSortTileMin;
+    h.clear = status_clear(b, RB);
     h.ctl = ctl;
     TraceScope ts(b.s, "hist");
     auto kern = hist_kernel<kSortBlock, kSortK, RB, B>;
@@ -513,9 +532,7 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
     }
     a.ctl = ctl;
     const bool regen = fused && p == 0;
-    const bool shaped = !regen;
-    const uint32_t pass_tiles =
-        static_cast<uint32_t>(ceil_div(npairs, shaped ? sort_shape_tile(g_sort_shape) : kSortTile));
+    const uint32_t pass_tiles = static_cast<uint32_t>(ceil_div(npairs, pass_tile(p)));
     TraceScope ts(b.s, regen ? "onesweep_expand" : (B && last) ? "onesweep_grids" : "onesweep");
     int st = launch_pass<B>(a, pass_bits(sp.width[p]), regen, B && last, pass_tiles, b.s);
     if (st) return st;

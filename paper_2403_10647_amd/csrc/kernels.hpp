@@ -55,6 +55,28 @@ GB_DEV uint32_t grid_search(const GridSet& s, uint32_t t) {
   }
 }
 
+// The look-back words the radix passes will use, cleared by the kernel that
+// runs before them: pass p uses ceil(NO / tile[p]) * radix[p] words from
+// status + p * stride.
+struct StatusClear {
+  uint64_t* status;
+  uint64_t stride;
+  uint32_t tile[4];
+  uint32_t radix[4];
+  uint32_t passes;
+};
+
+template <int Block>
+GB_DEV void clear_status(const StatusClear& c, uint64_t npairs) {
+  const uint64_t first = static_cast<uint64_t>(blockIdx.x) * Block + threadIdx.x;
+  const uint64_t step = static_cast<uint64_t>(gridDim.x) * Block;
+  for (uint32_t p = 0; p < c.passes; ++p) {
+    const uint64_t words = ((npairs + c.tile[p] - 1) / c.tile[p]) * c.radix[p];
+    uint64_t* st = c.status + p * c.stride;
+    for (uint64_t i = first; i < words; i += step) st[i] = 0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // CountCells + ExclusiveSum (one pass, decoupled look-back).
 // ---------------------------------------------------------------------------
@@ -451,9 +473,7 @@ struct ExpandOutArgs {
   uint32_t* objs;
   SortPlan plan;
   uint32_t* hist;           // [4][kRadixMax]
-  uint64_t* sort_status;    // [passes][status_stride]
-  uint64_t status_stride;
-  uint32_t clear_tile;      // smallest radix-pass tile: bounds the look-back words to clear
+  StatusClear clear;        // the radix passes' look-back words
   uint32_t vec16;           // cells and objs are 16-byte aligned
   Control* ctl;
 };
@@ -541,11 +561,7 @@ __global__ __launch_bounds__(Block, 4) void expand_kernel(ExpandOutArgs a) {
   const uint64_t npairs = a.ctl->npairs;
   const uint32_t ntiles = static_cast<uint32_t>((npairs + N - 1) / N);
   if constexpr (RB > 0) {
-    const uint64_t per_pass = ((npairs + a.clear_tile - 1) / a.clear_tile) * R;
-    const uint64_t nwords = static_cast<uint64_t>(a.plan.passes) * per_pass;
-    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * Block + threadIdx.x; i < nwords;
-         i += static_cast<uint64_t>(gridDim.x) * Block)
-      a.sort_status[(i / per_pass) * a.status_stride + i % per_pass] = 0;
+    clear_status<Block>(a.clear, npairs);
     for (int i = threadIdx.x; i < 4 * R; i += Block) s_hist[i] = 0;
   }
   while (true) {
@@ -594,9 +610,7 @@ struct HistArgs {
   ExpandArgs ex;
   SortPlan plan;
   uint32_t* hist;           // [4][kRadixMax]
-  uint64_t* sort_status;    // [passes][status_stride]
-  uint64_t status_stride;   // words per pass (capacity tiles * radix)
-  uint32_t clear_tile;      // smallest radix-pass tile: bounds the look-back words to clear
+  StatusClear clear;        // the radix passes' look-back words
   Control* ctl;
 };
 
@@ -611,14 +625,7 @@ __global__ __launch_bounds__(Block) void hist_kernel(HistArgs a) {
   if (build_failed(a.ctl)) return;
   const uint64_t npairs = a.ctl->npairs;
   const uint32_t ntiles = static_cast<uint32_t>((npairs + N - 1) / N);
-  // clear the sort passes' look-back words
-  {
-    const uint64_t per_pass = ((npairs + a.clear_tile - 1) / a.clear_tile) * R;
-    const uint64_t nwords = static_cast<uint64_t>(a.plan.passes) * per_pass;
-    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * Block + threadIdx.x; i < nwords;
-         i += static_cast<uint64_t>(gridDim.x) * Block)
-      a.sort_status[(i / per_pass) * a.status_stride + i % per_pass] = 0;
-  }
+  clear_status<Block>(a.clear, npairs);
   for (int i = threadIdx.x; i < 4 * R; i += Block) s_hist[i] = 0;
   __syncthreads();
   while (true) {
