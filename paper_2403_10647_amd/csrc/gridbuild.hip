@@ -20,18 +20,21 @@ using namespace gb;
 namespace {
 
 // ---- launch shapes ----------------------------------------------------------
-constexpr int kCountBlock = 256, kCountK = 8;           // 2048 triangles per count tile
-constexpr int kSortBlock = 512, kSortK = 16;            // 8192 pairs per sort tile
+constexpr int kCountBlock = 1024, kCountK = 8;          // 8192 triangles per count tile
+constexpr int kExpandBlock = 512, kExpandK = 8;         // 4096 pairs per expansion tile
+constexpr int kExpandTile = kExpandBlock * kExpandK;
+constexpr int kExpandTileShift = 12;                    // tfo/tfg hold one entry per expansion tile
+constexpr int kSortBlock = 512, kSortK = 16;            // radix tile shape 0 and the standalone sort: 8192 pairs
 constexpr int kSortTile = kSortBlock * kSortK;
-constexpr int kSortTileMin = 4096;                      // smallest tile of any radix-pass shape
-constexpr int kSortTileShift = 13;
+constexpr int kSortTileMin = 4096;                      // smallest tile of any radix-pass or expansion shape
 constexpr int kRangesBlock = 256, kRangesK = 16;        // 4096 merge items per range tile
 constexpr int kMergeTile = kRangesBlock * kRangesK;
 constexpr int kScanBlock = 256, kScanK = 8;
 constexpr int kPlanBlock = 1024;
 constexpr int kMaxRadixBits = 11;
 constexpr int kKeyMapBits = 13;                         // batched key map: at most 8192 buckets
-static_assert((1 << kSortTileShift) == kSortTile, "sort tile must be a power of two");
+static_assert((1 << kExpandTileShift) == kExpandTile, "expansion tile must be a power of two");
+static_assert(kExpandTile >= kSortTileMin && kSortTile >= kSortTileMin, "tile tables are sized by the smallest tile");
 
 #define GB_TRY(expr)                             \
   do {                                           \
@@ -273,7 +276,7 @@ int launch_count(Build& b) {
   a.tfo = at<uint32_t>(b.ws, b.L.tfo);
   a.tfg = at<uint32_t>(b.ws, b.L.tfg);
   a.ntfo = b.L.ntfo;
-  a.sort_tile_shift = kSortTileShift;
+  a.sort_tile_shift = kExpandTileShift;
   a.status = at<uint64_t>(b.ws, b.L.count_status);
   a.ctl = at<Control>(b.ws, b.L.ctl);
   TraceScope ts(b.s, "count_scan");
@@ -341,7 +344,7 @@ int pass_bits(uint32_t width);
 // Tile size of radix pass p under the current knobs (a regenerating first pass
 // reads the expansion's tiles; the others take the sort_shape tile).
 uint32_t pass_tile(uint32_t p) {
-  return (g_fused_expand && p == 0) ? static_cast<uint32_t>(kSortTile)
+  return (g_fused_expand && p == 0) ? static_cast<uint32_t>(kExpandTile)
                                     : static_cast<uint32_t>(sort_shape_tile(g_sort_shape));
 }
 
@@ -374,15 +377,15 @@ int launch_expand(Build& b, uint32_t* cells, uint32_t* objs, uint64_t npairs) {
   a.ctl = at<Control>(b.ws, b.L.ctl);
   {
     TraceScope ts(b.s, RB > 0 ? "expand_hist" : "expand");
-    auto kern = expand_kernel<kSortBlock, kSortK, RB, B>;
-    kern<<<resident_blocks(kern, kSortBlock, ceil_div(npairs, kSortTile)), kSortBlock, 0, b.s>>>(a);
+    auto kern = expand_kernel<kExpandBlock, kExpandK, RB, B>;
+    kern<<<resident_blocks(kern, kExpandBlock, ceil_div(npairs, kExpandTile)), kExpandBlock, 0, b.s>>>(a);
     GB_LAUNCHED();
   }
   if constexpr (B) {
     // the tiles that straddle grids, skipped above
     TraceScope ts(b.s, "expand_straddle");
-    auto kern = expand_straddle_kernel<kSortBlock, kSortK, RB>;
-    kern<<<static_cast<uint32_t>(std::min<uint64_t>(ceil_div(npairs, kSortTile), 1024)), kSortBlock, 0, b.s>>>(a);
+    auto kern = expand_straddle_kernel<kExpandBlock, kExpandK, RB>;
+    kern<<<static_cast<uint32_t>(std::min<uint64_t>(ceil_div(npairs, kExpandTile), 1024)), kExpandBlock, 0, b.s>>>(a);
     GB_LAUNCHED();
   }
   return GRID_OK;
@@ -413,9 +416,9 @@ void launch_shaped(const SortPassArgs& a, uint32_t ntiles, hipStream_t s) {
 template <int RB, bool B>
 int launch_pass_rb(const SortPassArgs& a, bool regen, bool to_grids, uint32_t ntiles, hipStream_t s) {
   if (regen) {
-    // regenerating passes read the expansion, whose tiles are kSortTile pairs
-    if (to_grids) launch_onesweep<kSortBlock, kSortK, RB, kFromExpansion, kToGrids, B>(a, ntiles, s);
-    else launch_onesweep<kSortBlock, kSortK, RB, kFromExpansion, kToArrays, B>(a, ntiles, s);
+    // regenerating passes read the expansion, whose tiles are kExpandTile pairs
+    if (to_grids) launch_onesweep<kExpandBlock, kExpandK, RB, kFromExpansion, kToGrids, B>(a, ntiles, s);
+    else launch_onesweep<kExpandBlock, kExpandK, RB, kFromExpansion, kToArrays, B>(a, ntiles, s);
   } else if (to_grids) {
     if constexpr (B) launch_shaped<RB, kToGrids, B>(a, ntiles, s);
     else return GRID_E_INVAL;  // plain builds end in the caller's arrays
@@ -483,7 +486,7 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
     int st = launch_sink(b);
     if (st) return st;
   }
-  const uint32_t ntiles = static_cast<uint32_t>(ceil_div(npairs, kSortTile));
+  const uint32_t ntiles = static_cast<uint32_t>(ceil_div(npairs, kExpandTile));
   Control* ctl = at<Control>(b.ws, b.L.ctl);
   const uint32_t P = sp.passes;
   const bool fused = g_fused_expand != 0;
@@ -497,8 +500,8 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
     h.clear = status_clear(b, RB);
     h.ctl = ctl;
     TraceScope ts(b.s, "hist");
-    auto kern = hist_kernel<kSortBlock, kSortK, RB, B>;
-    kern<<<resident_blocks(kern, kSortBlock, ntiles), kSortBlock, 0, b.s>>>(h);
+    auto kern = hist_kernel<kExpandBlock, kExpandK, RB, B>;
+    kern<<<resident_blocks(kern, kExpandBlock, ntiles), kExpandBlock, 0, b.s>>>(h);
     GB_LAUNCHED();
   } else {
     const Dest d = sort_dest(b, B, -1, P, out_cells, out_objs);

@@ -1,8 +1,9 @@
 """GPU parity: the HIP library against the CPU oracle, bit for bit.
 
 Every output is integer indexing plus one fixed FP32 sequence, so the
-tolerance is zero.  Sizes span several tiles (2048 triangles per count tile,
-8192 pairs per sort tile, 4096 merge items per range tile) with ragged tails.
+tolerance is zero.  Sizes span several tiles (8192 triangles per count tile,
+4096 pairs per expansion tile, 8192 to 16384 pairs per radix tile, 4096 merge
+items per range tile) with ragged tails.
 """
 import numpy as np
 import pytest
