@@ -207,14 +207,28 @@ class GridResult:
 
 
 def _input_args(g: GridInput):
+    """The C arguments of a grid (checked once, then kept while the tensors stay the same)."""
+    key = (g.verts.data_ptr(), g.tris.data_ptr(), g.verts.shape, g.tris.shape, tuple(g.lo), tuple(g.hi), tuple(g.res))
+    cached = getattr(g, "_c_args", None)
+    if cached is not None and cached[0] == key:
+        return cached[1]
     assert g.verts.dtype == torch.float32 and g.verts.is_contiguous() and g.verts.dim() == 2 and g.verts.shape[0] == 3
     assert g.tris.dtype == torch.int32 and g.tris.is_contiguous() and (g.tris.numel() == 0 or g.tris.shape[1] == 3)
-    return (C.c_void_p(g.verts.data_ptr()), C.c_uint32(g.nverts), C.c_void_p(g.tris.data_ptr()),
+    args = (C.c_void_p(g.verts.data_ptr()), C.c_uint32(g.nverts), C.c_void_p(g.tris.data_ptr()),
             C.c_uint32(g.ntris), _f3(g.lo), _f3(g.hi), _u3(g.res))
+    object.__setattr__(g, "_c_args", (key, args))
+    return args
+
+
+_ws_sizes: dict = {}
 
 
 def workspace_size(ntris: int, cap_pairs: int, res) -> int:
-    return int(lib().grid_workspace_size(ntris, cap_pairs, _u3(res)))
+    key = (int(ntris), int(cap_pairs), tuple(int(r) for r in res))
+    n = _ws_sizes.get(key)
+    if n is None:
+        n = _ws_sizes[key] = int(lib().grid_workspace_size(ntris, cap_pairs, _u3(res)))
+    return n
 
 
 def count(g: GridInput, ws: Optional[Workspace] = None, with_start: bool = False, stream=None):

@@ -160,8 +160,8 @@ Plan make_plan(uint32_t bits, int max_digit = -1) {
 // ---- workspace layout -----------------------------------------------------------
 struct Layout {
   size_t ctl, hist, count_status, zero_end;
-  size_t start, box, tfo, tfg, sort_status, keys_alt, vals_alt, keys_alt2, vals_alt2, run, npairs_out, splits, table, sink,
-      kmap, total;
+  size_t start, box, tfo, tfg, sort_status, keys_alt, vals_alt, keys_alt2, vals_alt2, run, npairs_out, splits,
+      tile_grid, table, sink, kmap, total;
   uint32_t ntfo, ncount_tiles, nsort_tiles_cap, nmerge_tiles_cap;
 };
 
@@ -196,6 +196,7 @@ Layout make_layout(uint64_t ntris, uint64_t cap_pairs, uint64_t ncells_plus_grid
   L.run = take((ngrids + 1) * sizeof(GridRun));
   L.npairs_out = take(ngrids * 8);
   L.splits = take(static_cast<size_t>(L.nmerge_tiles_cap) * 4);
+  L.tile_grid = take(batched ? static_cast<size_t>(L.nmerge_tiles_cap) * 4 : 0);
   L.table = take(batched ? ngrids * sizeof(GridDev) : 0);
   L.sink = take(batched ? ngrids * sizeof(GridSink) : 0);
   L.kmap = take(batched ? (size_t{1} << kKeyMapBits) * sizeof(uint2) : 0);
@@ -571,6 +572,7 @@ int launch_ranges(Build& b, uint64_t merge_items_cap) {
   a.gs = b.gs;
   a.run = at<GridRun>(b.ws, b.L.run);
   a.splits = at<uint32_t>(b.ws, b.L.splits);
+  a.tile_grid = at<uint32_t>(b.ws, b.L.tile_grid);
   a.merge_tile = kMergeTile;
   a.ctl = at<Control>(b.ws, b.L.ctl);
   const uint64_t tiles = ceil_div(merge_items_cap, kMergeTile) + b.gs.ngrids;

@@ -93,18 +93,35 @@ struct CountArgs {
   Control* ctl;
 };
 
-template <int Block, int K, bool Batched>
-__global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
-  constexpr int Tile = Block * K;
-  __shared__ uint32_t s_val[padded(Tile)];
-  __shared__ uint64_t s_wtot[Block / kWave];
-  __shared__ uint64_t s_prefix;
-  __shared__ uint32_t s_tile;
-  const uint32_t tile = next_tile(&a.ctl->tile_counter[kCtrCount], &s_tile);
+// Grid of triangle t (largest g with tri_base[g] <= t), found by one whole
+// wave: each level probes 64 evenly spaced grids of the remaining range at
+// once, so 512 grids take two dependent loads.  Every lane must pass the same
+// t; all lanes get the answer.
+GB_DEV uint32_t grid_of_tri_wave(const GridSet& s, uint32_t t) {
+  uint32_t lo = 0, end = s.ngrids;  // answer in [lo, end); tri_base[0] = 0 <= t
+  const uint32_t lane = lane_id();
+  while (end - lo > 1) {
+    const uint32_t step = (end - lo + kWave - 1) / kWave;
+    const uint32_t g = lo + lane * step;
+    const bool le = g < end && s.table[g].tri_base <= t;
+    const uint32_t c = static_cast<uint32_t>(__popcll(ballot(le)));  // probes are monotone: lanes 0..c-1
+    lo += (c - 1) * step;
+    end = lo + step < end ? lo + step : end;
+  }
+  return lo;
+}
+
+// Where count_items finds a triangle's grid: the plain build's one grid, the
+// one grid of a batched tile (loaded once, held in scalar registers), or a
+// per-triangle walk for batched tiles that straddle grids.
+enum CountMode : int { kCountPlain = 0, kCountOneGrid = 1, kCountPerItem = 2 };
+
+// CountCells for the tile's triangles base + k * Block + tid: writes each box
+// and leaves the counts in s_val (striped order).
+template <int Block, int K, int Mode>
+GB_DEV void count_items(const CountArgs& a, const GridDev& G0, uint64_t base, uint32_t* s_val) {
   const uint32_t tid = threadIdx.x;
-  const uint64_t base = static_cast<uint64_t>(tile) * Tile;
-  const uint32_t ntiles = (a.ntris + Tile - 1) / Tile;
-  uint32_t g = Batched && base < a.ntris ? grid_search<Batched>(a.gs, static_cast<uint32_t>(base)) : 0;
+  uint32_t g = Mode == kCountPerItem ? grid_search<true>(a.gs, static_cast<uint32_t>(base)) : 0;
 
   // all index loads, then all vertex loads, then the arithmetic
   uint32_t gi[K], idx[K][3];
@@ -112,9 +129,9 @@ __global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
   for (int k = 0; k < K; ++k) {
     const uint64_t t = base + static_cast<uint64_t>(k) * Block + tid;
     const uint32_t tc = static_cast<uint32_t>(t < a.ntris ? t : a.ntris - 1);
-    g = grid_of_tri<Batched>(a.gs, tc, g);
+    if constexpr (Mode == kCountPerItem) g = grid_of_tri<true>(a.gs, tc, g);
     gi[k] = g;
-    const GridDev& G = grid_at<Batched>(a.gs, g);
+    const GridDev& G = Mode == kCountPerItem ? a.gs.table[g] : G0;
     const uint32_t* tri = G.tris + 3 * static_cast<uint64_t>(tc - G.tri_base);
     idx[k][0] = tri[0];
     idx[k][1] = tri[1];
@@ -124,7 +141,7 @@ __global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
   bool bad[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const GridDev& G = grid_at<Batched>(a.gs, gi[k]);
+    const GridDev& G = Mode == kCountPerItem ? a.gs.table[gi[k]] : G0;
     bad[k] = idx[k][0] >= G.nverts || idx[k][1] >= G.nverts || idx[k][2] >= G.nverts;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
@@ -138,7 +155,7 @@ __global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
     const uint64_t t = base + static_cast<uint64_t>(k) * Block + tid;
     uint32_t cnt = 0;
     if (t < a.ntris) {
-      const GridDev& G = grid_at<Batched>(a.gs, gi[k]);
+      const GridDev& G = Mode == kCountPerItem ? a.gs.table[gi[k]] : G0;
       uint64_t packed = 0;
       cnt = 1;
       if (bad[k]) {
@@ -160,6 +177,35 @@ __global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
       a.box[t] = packed;
     }
     s_val[pad32(k * Block + tid)] = cnt;
+  }
+}
+
+template <int Block, int K, bool Batched>
+__global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
+  constexpr int Tile = Block * K;
+  __shared__ uint32_t s_val[padded(Tile)];
+  __shared__ uint64_t s_wtot[Block / kWave];
+  __shared__ uint64_t s_prefix;
+  __shared__ uint32_t s_tile;
+  const uint32_t tile = next_tile(&a.ctl->tile_counter[kCtrCount], &s_tile);
+  const uint32_t tid = threadIdx.x;
+  const uint64_t base = static_cast<uint64_t>(tile) * Tile;
+  const uint32_t ntiles = (a.ntris + Tile - 1) / Tile;
+  if constexpr (Batched) {
+    // the tile is the same for the whole workgroup, and so are its grids
+    const uint32_t t0 = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(base < a.ntris ? base : a.ntris - 1));
+    const uint64_t e = base + Tile < a.ntris ? base + Tile : a.ntris;
+    const uint32_t t1 = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(e - 1));
+    const uint32_t gl = __builtin_amdgcn_readfirstlane(grid_of_tri_wave(a.gs, t0));
+    const bool one = gl + 1 >= a.gs.ngrids || a.gs.table[gl + 1].tri_base > t1;
+    if (one) {
+      const GridDev G = a.gs.table[gl];
+      count_items<Block, K, kCountOneGrid>(a, G, base, s_val);
+    } else {
+      count_items<Block, K, kCountPerItem>(a, a.gs.table[gl], base, s_val);
+    }
+  } else {
+    count_items<Block, K, kCountPlain>(a, a.gs.one, base, s_val);
   }
   __syncthreads();
 

@@ -150,6 +150,7 @@ struct RangesArgs {
   GridSet gs;
   const GridRun* run;
   uint32_t* splits;        // [total merge tiles] pair index at each tile's start
+  uint32_t* tile_grid;     // [total merge tiles] batched: grid of each tile (written by split_kernel)
   uint32_t merge_tile;
   Control* ctl;
 };
@@ -177,6 +178,7 @@ __global__ __launch_bounds__(Block) void split_kernel(RangesArgs a) {
     const uint64_t ncell = static_cast<uint64_t>(gd.res[0]) * gd.res[1] * gd.res[2];
     const uint64_t d = static_cast<uint64_t>(b - a.run[g].mtile_base) * a.merge_tile;
     a.splits[b] = merge_split(gd.out_cells, a.run[g].npairs, ncell + 1, d);
+    if constexpr (Batched) a.tile_grid[b] = g;
   }
 }
 
@@ -191,7 +193,7 @@ __global__ __launch_bounds__(Block) void ranges_kernel(RangesArgs a) {
   const uint32_t tid = threadIdx.x;
   // tiles are independent: a static stride over them, no tile counter
   for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
-    const uint32_t g = Batched ? grid_of_mtile(a.run, G, b) : 0;
+    const uint32_t g = Batched ? __builtin_amdgcn_readfirstlane(a.tile_grid[b]) : 0;
     const GridDev& gd = grid_at<Batched>(a.gs, g);
     const GridRun& gr = a.run[g];
     const uint64_t ncell = static_cast<uint64_t>(gd.res[0]) * gd.res[1] * gd.res[2];
