@@ -265,6 +265,30 @@ def build(g: GridInput, cap_pairs: Optional[int] = None, ws: Optional[Workspace]
     return out
 
 
+class PlainBuild:
+    """grid_build of one input into one output, its C arguments marshalled once.
+
+    For repeated builds of the same buffers (frames of a scene, benchmarks):
+    each call is one C call.  The input tensors, the outputs and the workspace
+    must stay alive and in place while the object is used."""
+
+    def __init__(self, g: GridInput, out: GridResult, ws: Optional[Workspace] = None, stream=None):
+        self.g, self.out = g, out
+        self.ws = ws or default_workspace(g.verts.device)
+        cap = int(out.cells.numel())
+        wp, wn = self.ws.ptr_size(workspace_size(g.ntris, cap, g.res))
+        self._o = grid_out(out.cells.data_ptr(), out.objs.data_ptr(), out.ranges.data_ptr(), cap, 0)
+        self._fn = lib().grid_build
+        self._args = (*_input_args(g), wp, wn, C.byref(self._o), _stream(stream))
+
+    def __call__(self) -> GridResult:
+        st = self._fn(*self._args)
+        self.out.npairs = int(self._o.npairs)
+        if st != GRID_OK:
+            raise GridError(st, "grid_build")
+        return self.out
+
+
 def expand(g: GridInput, ws: Optional[Workspace] = None, stream=None):
     """Object-order (cells, objs) lists."""
     L = lib()

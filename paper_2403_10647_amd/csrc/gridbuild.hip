@@ -147,13 +147,17 @@ Plan make_plan(uint32_t bits, int max_digit = -1) {
   // at most 4 passes (the plan's arrays and the histogram slots): a narrow
   // digit limit on a wide key widens the digits instead (32 bits / 4 = 8)
   const uint32_t passes = std::min<uint32_t>(4, (bits + md - 1) / md);
-  const uint32_t w = (bits + passes - 1) / passes;
+  // widths as even as possible (25 bits: 9, 8, 8): a wider digit costs its
+  // pass more counters, look-back words and shorter scatter runs
+  const uint32_t base = bits / passes, extra = bits % passes;
   p.sp.passes = passes;
+  uint32_t shift = 0;
   for (uint32_t i = 0; i < passes; ++i) {
-    p.sp.shift[i] = i * w;
-    p.sp.width[i] = std::min(w, bits - i * w);
+    p.sp.shift[i] = shift;
+    p.sp.width[i] = base + (i < extra ? 1u : 0u);
+    shift += p.sp.width[i];
   }
-  p.rb = std::max(8, static_cast<int>(w));
+  p.rb = std::max(8, static_cast<int>(base + (extra ? 1u : 0u)));
   return p;
 }
 

@@ -98,9 +98,7 @@ def tune_plain(g, reps: int = 5, space=None, cache_path: Optional[str] = None, G
     ws = G.Workspace()
     npairs, _ = G.count(g, ws)
     out = G.build(g, cap_pairs=npairs, ws=ws)
-
-    def run():
-        return G.build(g, ws=ws, out=out)
+    run = G.PlainBuild(g, out, ws)
 
     def snapshot():
         return [t.clone() for t in (out.cells[:out.npairs], out.objs[:out.npairs], out.ranges)]

@@ -323,3 +323,21 @@ def test_build_under_every_sort_shape(G, shape):
     finally:
         G.tune_set("sort_shape", 3)
         G.tune_set("max_digit_bits", 9)
+
+
+def test_plain_build_object_repeats(G):
+    # the marshalled-once build equals G.build and the oracle, call after call
+    s = scenes.make_scene("mixed", ntris=30_000)
+    g = G.GridInput.from_scene(s)
+    no, _ = G.count(g)
+    out = G.build(g, cap_pairs=no)
+    ref = [x.copy() for x in out.numpy()]
+    b = G.PlainBuild(g, out)
+    for _ in range(3):
+        out.cells.fill_(0)
+        r = b()
+        assert r.npairs == no
+        for x, y in zip(ref, r.numpy()):
+            assert np.array_equal(x, y)
+    oc, oo, orr = oracle.build_scene(s)
+    assert np.array_equal(ref[0], oc) and np.array_equal(ref[1], oo) and np.array_equal(ref[2], orr)
