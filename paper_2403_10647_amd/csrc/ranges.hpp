@@ -185,8 +185,12 @@ __global__ __launch_bounds__(Block) void split_kernel(RangesArgs a) {
 template <int Block, int K, bool Batched>
 __global__ __launch_bounds__(Block) void ranges_kernel(RangesArgs a) {
   constexpr int D = Block * K;
-  __shared__ uint32_t s_cells[D];
-  __shared__ uint32_t s_begin[D];
+  static_assert(D < 65535, "tile-relative cells and pair offsets are held in 16 bits");
+  // Within a tile the pairs' cells lie in [i0 - 1, i1 - 1] and the begins in
+  // [j0, j1], so both are kept relative to the tile in 16 bits: half the LDS
+  // of 32-bit copies, so every persistent block of a CU stays resident.
+  __shared__ uint16_t s_cells[D];   // cell + 1 - i0
+  __shared__ uint16_t s_begin[D];   // begin - j0
   if (build_failed(a.ctl)) return;
   const uint32_t G = a.gs.ngrids;
   const uint32_t total = a.run[G].mtile_base;
@@ -205,6 +209,7 @@ __global__ __launch_bounds__(Block) void ranges_kernel(RangesArgs a) {
     const uint64_t j1 = lb + 1 < gr.mtiles ? a.splits[b + 1] : gr.npairs;
     const uint64_t i0 = d0 - j0, i1 = d1 - j1;
     const uint32_t np = static_cast<uint32_t>(j1 - j0), ne = static_cast<uint32_t>(i1 - i0);
+    const uint32_t cbase = static_cast<uint32_t>(i0) - 1u;  // cells of the tile's pairs are >= i0 - 1
     // all K loads of a thread in flight at once (np <= D = Block * K)
     uint32_t cv[K];
 #pragma unroll
@@ -215,23 +220,25 @@ __global__ __launch_bounds__(Block) void ranges_kernel(RangesArgs a) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const uint32_t p = k * Block + tid;
-      if (p < np) s_cells[p] = cv[k];
+      if (p < np) s_cells[p] = static_cast<uint16_t>(cv[k] - cbase);
     }
     __syncthreads();
-    // this thread's stretch of the tile's diagonal
+    // this thread's stretch of the tile's diagonal; in relative terms pair p
+    // precedes event e when cell(p) < i0 + e, i.e. s_cells[p] <= e
     const uint32_t dd0 = tid * K;
     const uint32_t nd = np + ne;
     if (dd0 < nd) {
+      // first pair index p with cell(p) + (j0 + p) + 1 >= d0 + dd0, i.e. s_cells[p] + p >= dd0
       uint32_t lo = dd0 > ne ? dd0 - ne : 0, hi = dd0 < np ? dd0 : np;
       while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (static_cast<uint64_t>(s_cells[mid]) + j0 + mid + 1 >= d0 + dd0) hi = mid; else lo = mid + 1;
+        if (static_cast<uint32_t>(s_cells[mid]) + mid >= dd0) hi = mid; else lo = mid + 1;
       }
       uint32_t p = lo, e = dd0 - lo;
       const uint32_t dend = dd0 + K < nd ? dd0 + K : nd;
       for (uint32_t dd = dd0; dd < dend; ++dd) {
-        if (e < ne && (p >= np || i0 + e <= s_cells[p])) {
-          s_begin[e] = static_cast<uint32_t>(j0 + p);
+        if (e < ne && (p >= np || e + 1 <= s_cells[p])) {
+          s_begin[e] = static_cast<uint16_t>(p);
           ++e;
         } else {
           ++p;
@@ -247,7 +254,7 @@ __global__ __launch_bounds__(Block) void ranges_kernel(RangesArgs a) {
 #pragma unroll
     for (int k = 0; k < 2 * K; ++k) {
       const uint64_t q = q0 + static_cast<uint64_t>(k) * Block + tid;
-      if (q < q1) gd.out_ranges[q] = s_begin[(q + 1) / 2 - i0];
+      if (q < q1) gd.out_ranges[q] = static_cast<uint32_t>(j0) + s_begin[(q + 1) / 2 - i0];
     }
     __syncthreads();
   }
