@@ -530,6 +530,33 @@ GB_DEV bool tile_straddles(const ExpandArgs& a, uint32_t tile, uint32_t ntiles) 
   return a.tfg[tile] != hi;
 }
 
+// Digit histograms of every pass for a thread's K consecutive keys (blocked
+// layout): consecutive pairs of one object mostly share their upper digits, so
+// each run of equal digits is added once.
+template <int Block, int K, int RB>
+GB_DEV void hist_runs(const SortPlan& plan, const uint32_t (&keys)[K], uint32_t n, uint32_t* s_hist) {
+  constexpr int R = 1 << RB;
+  const uint32_t first = threadIdx.x * K;
+  const uint32_t m = first < n ? (n - first < K ? n - first : K) : 0;
+  for (uint32_t p = 0; p < plan.passes; ++p) {
+    const uint32_t sh = plan.shift[p], dm = (1u << plan.width[p]) - 1u;
+    uint32_t cur = 0, cnt = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (static_cast<uint32_t>(k) < m) {
+        const uint32_t d = (keys[k] >> sh) & dm;
+        if (cnt != 0 && d != cur) {
+          atomicAdd(&s_hist[p * R + cur], cnt);
+          cnt = 0;
+        }
+        cur = d;
+        ++cnt;
+      }
+    }
+    if (cnt != 0) atomicAdd(&s_hist[p * R + cur], cnt);
+  }
+}
+
 // Store a tile's pairs (a thread's K consecutive pairs, 16-byte stores when
 // all are present) and add its digits to the block's histograms.
 template <int Block, int K, int RB>
@@ -556,28 +583,7 @@ GB_DEV void store_tile(const ExpandOutArgs& a, uint32_t tile, uint32_t n, const 
       }
     }
   }
-  if constexpr (RB > 0) {
-    // digit histograms: consecutive pairs of one object mostly share their
-    // upper digits, so each run of equal digits is added once
-    const uint32_t m = first < n ? (n - first < K ? n - first : K) : 0;
-    for (uint32_t p = 0; p < a.plan.passes; ++p) {
-      const uint32_t sh = a.plan.shift[p], dm = (1u << a.plan.width[p]) - 1u;
-      uint32_t cur = 0, cnt = 0;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        if (static_cast<uint32_t>(k) < m) {
-          const uint32_t d = (keys[k] >> sh) & dm;
-          if (cnt != 0 && d != cur) {
-            atomicAdd(&s_hist[p * R + cur], cnt);
-            cnt = 0;
-          }
-          cur = d;
-          ++cnt;
-        }
-      }
-      if (cnt != 0) atomicAdd(&s_hist[p * R + cur], cnt);
-    }
-  }
+  if constexpr (RB > 0) hist_runs<Block, K, RB>(a.plan, keys, n, s_hist);
 }
 
 template <int RB, int Block>
@@ -677,20 +683,11 @@ __global__ __launch_bounds__(Block) void hist_kernel(HistArgs a) {
   while (true) {
     const uint32_t tile = next_tile(&a.ctl->tile_counter[kCtrHist], &s_tile);
     if (tile >= ntiles) break;
+    // blocked layout: GlobalCoords stepped along each thread's run of slots,
+    // and each run of equal digits added once
     uint32_t keys[K], vals[K];
-    expand_tile<Block, K, Batched>(a.ex, tile, npairs, ntiles, s_owner, s_wtot, keys, vals);
-    const uint64_t base = static_cast<uint64_t>(tile) * N;
-    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const uint64_t i = base + w * (kWave * K) + k * kWave + lane;
-      if (i < npairs) {
-        for (uint32_t p = 0; p < a.plan.passes; ++p) {
-          const uint32_t d = (keys[k] >> a.plan.shift[p]) & ((1u << a.plan.width[p]) - 1u);
-          atomicAdd(&s_hist[p * R + d], 1u);
-        }
-      }
-    }
+    const uint32_t n = expand_tile<Block, K, Batched, kBlocked>(a.ex, tile, npairs, ntiles, s_owner, s_wtot, keys, vals);
+    hist_runs<Block, K, RB>(a.plan, keys, n, s_hist);
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < a.plan.passes * R; i += Block) {

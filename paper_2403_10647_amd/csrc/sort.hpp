@@ -42,7 +42,9 @@ __global__ __launch_bounds__(Block, Source == kFromArrays ? 4 : 2) void onesweep
   // staging (keys then values) doubles as the per-wave digit counters and the
   // expansion's owner slots
   constexpr int kStage0 = 2 * N > W * R ? 2 * N : W * R;
-  constexpr int kStage = kStage0 > padded(N) ? kStage0 : padded(N);  // also the expansion's padded slots
+  // also the expansion's padded slots and, when regenerating, its padded transpose
+  constexpr int kStage1 = Source == kFromExpansion ? 2 * padded(N) : padded(N);
+  constexpr int kStage = kStage0 > kStage1 ? kStage0 : kStage1;
   __shared__ uint32_t s_stage[kStage];
   __shared__ uint32_t s_tile_excl[R];
   __shared__ uint32_t s_dst[R];
@@ -65,7 +67,22 @@ __global__ __launch_bounds__(Block, Source == kFromArrays ? 4 : 2) void onesweep
 
     uint32_t keys[K], vals[K];
     if constexpr (Source == kFromExpansion) {
-      expand_tile<Block, K, Batched>(a.ex, tile, n, ntiles, s_stage, s_wtot, keys, vals);
+      // blocked expansion (GlobalCoords stepped along each thread's slots),
+      // then through LDS into the wave-striped order the stable rank needs
+      expand_tile<Block, K, Batched, kBlocked>(a.ex, tile, n, ntiles, s_stage, s_wtot, keys, vals);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        s_stage[pad32(tid * K + k)] = keys[k];
+        s_stage[padded(N) + pad32(tid * K + k)] = vals[k];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const uint32_t slot = w * (kWave * K) + k * kWave + lane;
+        keys[k] = s_stage[pad32(slot)];
+        vals[k] = s_stage[padded(N) + pad32(slot)];
+      }
+      __syncthreads();  // s_stage becomes the rank's counters
     } else {
       // branch-free loads (the tail re-reads the last element) keep all of
       // them in flight at once; the values are loaded after the rank, which
