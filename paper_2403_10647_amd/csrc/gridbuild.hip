@@ -281,7 +281,7 @@ int launch_count(Build& b) {
   a.tfo = at<uint32_t>(b.ws, b.L.tfo);
   a.tfg = at<uint32_t>(b.ws, b.L.tfg);
   a.ntfo = b.L.ntfo;
-  a.sort_tile_shift = kExpandTileShift;
+  a.tile_shift = kExpandTileShift;
   a.status = at<uint64_t>(b.ws, b.L.count_status);
   a.ctl = at<Control>(b.ws, b.L.ctl);
   TraceScope ts(b.s, "count_scan");

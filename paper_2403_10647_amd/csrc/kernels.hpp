@@ -85,10 +85,10 @@ struct CountArgs {
   uint32_t ntris;           // total triangles (all grids)
   uint32_t* start;          // [ntris] exclusive pair offsets (global)
   uint64_t* box;            // [ntris] packed cell boxes
-  uint32_t* tfo;            // [ntfo] owner of the first pair of each sort tile
+  uint32_t* tfo;            // [ntfo] owner of the first pair of each expansion tile
   uint32_t* tfg;            // [ntfo] batched: grid of that owner
   uint32_t ntfo;
-  uint32_t sort_tile_shift; // log2 of the sort tile size
+  uint32_t tile_shift;      // log2 of the expansion tile size (one tfo entry per expansion tile)
   uint64_t* status;         // [count tiles] look-back words
   Control* ctl;
 };
@@ -228,15 +228,15 @@ __global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
   __syncthreads();
   excl += s_prefix;
 
-  const uint64_t tmask = (uint64_t{1} << a.sort_tile_shift) - 1;
+  const uint64_t tmask = (uint64_t{1} << a.tile_shift) - 1;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const uint64_t t = base + static_cast<uint64_t>(tid) * K + k;
     s_val[pad32(tid * K + k)] = static_cast<uint32_t>(excl);
     if (mine[k] != 0 && t < a.ntris) {
-      // sort tiles whose first pair this object owns
-      uint64_t j = (excl + tmask) >> a.sort_tile_shift;
-      const uint64_t jlast = (excl + mine[k] - 1) >> a.sort_tile_shift;
+      // expansion tiles whose first pair this object owns
+      uint64_t j = (excl + tmask) >> a.tile_shift;
+      const uint64_t jlast = (excl + mine[k] - 1) >> a.tile_shift;
       if (j <= jlast && j < a.ntfo) {
         const uint32_t g = grid_search<Batched>(a.gs, static_cast<uint32_t>(t));  // rare: about one object per tile
         for (; j <= jlast && j < a.ntfo; ++j) {
@@ -256,9 +256,10 @@ __global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Expansion of one sort tile: pairs [tile * N, tile * N + n) -> (key, value),
-// in the wave-striped layout (item k of lane l in wave w is pair
-// tile * N + w * 64 * K + k * 64 + l).
+// Expansion of one tile of N = Block * K pairs (N must be the expansion tile
+// the count indexed tfo by): pairs [tile * N, tile * N + n) -> (key, value),
+// blocked (item k of thread t is pair tile * N + t * K + k) or wave-striped
+// (item k of lane l in wave w is pair tile * N + w * 64 * K + k * 64 + l).
 //
 // The owner of each pair is found as in the paper's MakeObjectIds +
 // InclusiveSum, in its max form: every object writes its id at its first pair
