@@ -46,12 +46,18 @@ def kernel_bytes(name: str, T: int, NO: int, R: int) -> float:
 
 
 def source_hash() -> str:
+    """Hash of the kernel sources' code (comments and whitespace left out), which
+    ties the committed traffic counters to the kernels they were taken on."""
     import hashlib
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2403_10647_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+        with open(os.path.join(csrc, f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(f.encode() + " ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
