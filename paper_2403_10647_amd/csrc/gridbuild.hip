@@ -165,7 +165,7 @@ Plan make_plan(uint32_t bits, int max_digit = -1) {
 struct Layout {
   size_t ctl, hist, count_status, zero_end;
   size_t start, box, tfo, tfg, sort_status, keys_alt, vals_alt, keys_alt2, vals_alt2, run, npairs_out, splits,
-      tile_grid, table, sink, kmap, total;
+      tile_grid, table, sink, kmap, ksink, total;
   uint32_t ntfo, ncount_tiles, nsort_tiles_cap, nmerge_tiles_cap;
 };
 
@@ -204,6 +204,7 @@ Layout make_layout(uint64_t ntris, uint64_t cap_pairs, uint64_t ncells_plus_grid
   L.table = take(batched ? ngrids * sizeof(GridDev) : 0);
   L.sink = take(batched ? ngrids * sizeof(GridSink) : 0);
   L.kmap = take(batched ? (size_t{1} << kKeyMapBits) * sizeof(uint2) : 0);
+  L.ksink = take(batched ? (size_t{1} << kKeyMapBits) * sizeof(GridSink) : 0);
   L.total = o + 256;
   return L;
 }
@@ -473,6 +474,7 @@ int launch_sink(Build& b) {
   a.run = at<GridRun>(b.ws, b.L.run);
   a.sink = at<GridSink>(b.ws, b.L.sink);
   a.kmap = at<uint2>(b.ws, b.L.kmap);
+  a.ksink = at<GridSink>(b.ws, b.L.ksink);
   a.kshift = kbits > static_cast<uint32_t>(kKeyMapBits) ? kbits - kKeyMapBits : 0;
   a.ncells = b.batch_cells;
   a.nbuckets = static_cast<uint32_t>(((b.batch_cells - 1) >> a.kshift) + 1);
@@ -534,6 +536,7 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
     a.counter = kCtrSort0 + p;
     a.sink = at<GridSink>(b.ws, b.L.sink);
     a.kmap = at<uint2>(b.ws, b.L.kmap);
+    a.ksink = at<GridSink>(b.ws, b.L.ksink);
     {
       const uint32_t kbits = bits_for(b.batch_cells);
       a.kshift = kbits > static_cast<uint32_t>(kKeyMapBits) ? kbits - kKeyMapBits : 0;

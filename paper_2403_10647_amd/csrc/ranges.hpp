@@ -78,7 +78,7 @@ struct alignas(16) GridSink {
   uint32_t* objs;
   uint64_t pair_base;
   uint32_t cell_base;
-  uint32_t pad;
+  uint32_t straddles;      // in the key map: the bucket holds more than one grid's keys
 };
 
 // Sort keys number the cells of all grids of a batch in one space.  Bucket j
@@ -89,7 +89,8 @@ struct SinkArgs {
   GridSet gs;
   const GridRun* run;
   GridSink* sink;          // [ngrids]
-  uint2* kmap;             // [nbuckets]
+  uint2* kmap;             // [nbuckets] grids of the bucket's first and last key
+  GridSink* ksink;         // [nbuckets] the sink of the bucket's first grid, straddles set if it has several
   uint32_t nbuckets;
   uint32_t kshift;
   uint64_t ncells;         // cells of the batch: every key is below it
@@ -116,14 +117,24 @@ __global__ __launch_bounds__(Block) void sink_kernel(SinkArgs a) {
     k.objs = d.out_objs;
     k.pair_base = a.run[g].pair_base;
     k.cell_base = static_cast<uint32_t>(d.cell_base);
-    k.pad = 0;
+    k.straddles = 0;
     a.sink[g] = k;
   }
   for (uint32_t j = first; j < a.nbuckets; j += stride) {
     const uint64_t k0 = static_cast<uint64_t>(j) << a.kshift;
     const uint64_t k1e = (static_cast<uint64_t>(j + 1) << a.kshift) - 1;
     const uint64_t k1 = k1e < a.ncells - 1 ? k1e : a.ncells - 1;
-    a.kmap[j] = make_uint2(grid_of_cell(a.gs, k0), grid_of_cell(a.gs, k1));
+    const uint32_t glo = grid_of_cell(a.gs, k0), ghi = grid_of_cell(a.gs, k1);
+    a.kmap[j] = make_uint2(glo, ghi);
+    // the bucket's own copy of its first grid's sink: one load for most keys
+    const GridDev& d = a.gs.table[glo];
+    GridSink k;
+    k.cells = d.out_cells;
+    k.objs = d.out_objs;
+    k.pair_base = a.run[glo].pair_base;
+    k.cell_base = static_cast<uint32_t>(d.cell_base);
+    k.straddles = glo != ghi ? 1u : 0u;
+    a.ksink[j] = k;
   }
 }
 

@@ -27,6 +27,7 @@ struct SortPassArgs {
   uint32_t counter;         // tile-counter slot
   const GridSink* sink;     // kToGrids: each grid's outputs, first pair and first cell
   const uint2* kmap;        // kToGrids: key bucket -> (first, last) grid
+  const GridSink* ksink;    // kToGrids: key bucket -> its first grid's sink (straddles: search)
   uint32_t kshift;          // kToGrids: key bucket = key >> kshift
   Control* ctl;
 };
@@ -244,20 +245,21 @@ __global__ __launch_bounds__(Block, Source == kFromArrays ? 4 : 2) void onesweep
       constexpr int C = 4;
       for (uint32_t i0 = tid; i0 < nt; i0 += C * Block) {
         uint32_t kk[C], vv[C];
-        uint2 km[C];
+        GridSink sk[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           const uint32_t i = i0 + c * Block;
           const uint32_t ii = i < nt ? i : nt - 1;  // past the tail: a valid slot, nothing stored
           kk[c] = s_stage[ii];
           vv[c] = s_stage[N + ii];
-          km[c] = a.kmap[kk[c] >> a.kshift];
+          sk[c] = a.ksink[kk[c] >> a.kshift];
         }
-        GridSink sk[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          const uint32_t g = km[c].x == km[c].y ? km[c].x : sink_of_key(a.sink, kk[c], km[c].x, km[c].y);
-          sk[c] = a.sink[g];
+          if (sk[c].straddles) {  // a bucket a grid boundary crosses (rare)
+            const uint2 km = a.kmap[kk[c] >> a.kshift];
+            sk[c] = a.sink[sink_of_key(a.sink, kk[c], km.x, km.y)];
+          }
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
