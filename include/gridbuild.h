@@ -121,8 +121,11 @@ int grid_expand(const float *verts_soa, uint32_t nverts, const uint32_t *tris, u
 /* Batched builds: ngrids independent grids (host array of descriptors) built
  * in one fixed sequence of launches.  Every grid's outputs are identical to
  * what grid_build returns for it alone: object ids local to the grid, ranges
- * relative to the grid's own pair list.  Pairs are sorted on a packed key
- * (grid index above the cell id) over only the bits in use. */
+ * relative to the grid's own pair list.  Internally the cells of all grids are
+ * numbered in one space (each grid's cells follow the previous grid's) and the
+ * pairs are sorted on that 32-bit number over only the bits in use, so one
+ * launch sequence holds at most 2^32 cells in total; grid_count_batched and
+ * grid_build_batched split larger batches into runs that fit. */
 /* Workspace for the batch as described (out.cap_pairs as set; output pointers
  * may still be NULL when only counting).  0 if a descriptor is invalid. */
 size_t grid_workspace_size_batched(const grid_desc *grids, uint32_t ngrids);
@@ -138,7 +141,7 @@ int grid_build_batched(grid_desc *grids, uint32_t ngrids, void *ws, size_t ws_by
 /* Batched build with no host synchronisation, for overlapping batches on
  * several streams (serving) and for stream capture.  Every grid's
  * out.cap_pairs must already hold at least its NO (from grid_count_batched);
- * the batch's packed keys must fit in 32 bits (GRID_E_INVAL otherwise: split
+ * the batch's cells must total at most 2^32 (GRID_E_INVAL otherwise: split
  * the batch).  host_staging is caller-owned pinned host memory of at least
  * grid_batch_staging_size(ngrids) bytes, which must stay untouched until the
  * stream has passed this call.  Errors found on the device (a bad vertex
@@ -203,7 +206,8 @@ int grid_sort_plan(uint32_t nbits, uint32_t *passes, uint32_t widths[4], uint32_
 
 /* Per-kernel totals collected while tracing is on. */
 typedef struct grid_trace_entry {
-  char name[48];       /* kernel: count_scan, plan, hist, onesweep_expand, onesweep, split, ranges, ... */
+  char name[48];       /* kernel: zero, count_scan, plan, sink, expand_hist, expand_straddle, hist,
+                          onesweep_expand, onesweep, onesweep_grids, split, ranges */
   uint32_t launches;   /* launches since the last read */
   double total_ms;     /* summed event-measured duration */
 } grid_trace_entry;
