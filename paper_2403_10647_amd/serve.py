@@ -160,6 +160,22 @@ class Server:
         self.count_ws = G.Workspace(self.device)
         self.out_budget = self.budget - self.ws_bytes * nslots
 
+    # -- admission count -----------------------------------------------------
+    def _count(self, new: List[Request]) -> List[int]:
+        """Pair counts of newly arrived requests, counted together; if that fails, one
+        by one, so a bad request fails alone (its entry is then its negative status)."""
+        try:
+            return G.count_batched([r.inp for r in new], self.count_ws, self.count_stream)
+        except G.GridError:
+            pass
+        out = []
+        for r in new:
+            try:
+                out.append(G.count_batched([r.inp], self.count_ws, self.count_stream)[0])
+            except G.GridError as e:
+                out.append(e.status)
+        return out
+
     # -- one batch ---------------------------------------------------------
     def _launch(self, slot: _Slot, batch: List[Request]) -> List[Request]:
         """Launch ``batch`` on ``slot``; returns the requests that could not be launched."""
@@ -259,14 +275,10 @@ class Server:
             if j > nxt:
                 new = reqs[nxt:j]
                 nxt = j
-                try:
-                    caps = G.count_batched([r.inp for r in new], self.count_ws, self.count_stream)
-                except G.GridError as e:
-                    caps = None
-                    err = e.status
+                caps = self._count(new)
                 for k, r in enumerate(new):
-                    if caps is None:
-                        r.status = err
+                    if caps[k] < 0:            # this request's own count failed (e.g. a bad vertex index)
+                        r.status = caps[k]
                         r.done = clock() - t0
                         finished += 1
                         continue

@@ -111,3 +111,23 @@ def test_request_above_budget_is_rejected(G, workload):
     rej = [r for r in reqs if r.status != G.GRID_OK]
     assert len(rej) == 1 and rej[0].key == len(pool) and rej[0].status == G.GRID_E_NOMEM
     _check_alone(G, [r for r in reqs if r.status == G.GRID_OK], refs)
+
+
+def test_bad_request_fails_alone(G, workload):
+    # a request with an out-of-range vertex index is rejected by its own count;
+    # the requests that arrived with it are served as usual
+    from paper_2403_10647_amd import serve
+    _, _, pool, big, refs = workload
+    reqs = serve.make_requests(pool, rate=4000.0, duration=0.02, seed=10, burst=True)
+    assert len(reqs) > 5
+    bad_tris = pool[3].tris.clone()
+    bad_tris[11, 2] = pool[3].nverts + 7
+    bad = G.GridInput(pool[3].verts, bad_tris, pool[3].lo, pool[3].hi, pool[3].res)
+    reqs.append(serve.Request(len(reqs), 0.0, bad, -1))
+    caps = [r.npairs for r in refs]
+    ws = serve.batch_workspace_bytes(pool, caps[:-1])
+    srv = serve.Server(4 * ws, ws, nslots=2, max_pairs=1 << 20, references=None, keep_results=True)
+    st = srv.run(reqs)
+    assert st.failed == 1 and st.completed == len(reqs) - 1
+    assert reqs[-1].status == G.GRID_E_BADINDEX
+    _check_alone(G, reqs[:-1], refs)
