@@ -183,7 +183,7 @@ Layout make_layout(uint64_t ntris, uint64_t cap_pairs, uint64_t ncells_plus_grid
   L.ntfo = L.nsort_tiles_cap + 1;
   L.nmerge_tiles_cap = static_cast<uint32_t>(ceil_div(ncells_plus_grids + cap_pairs, kMergeTile) + ngrids);
   L.ctl = take(sizeof(Control));
-  L.hist = take(4 * kRadixMax * sizeof(uint32_t));
+  L.hist = take(static_cast<size_t>(kHistCopies) * 4 * kRadixMax * sizeof(uint32_t));
   L.count_status = take(std::max<size_t>(L.ncount_tiles, 1) * 8);
   L.zero_end = o;
   L.start = take(ntris * 4);
@@ -528,6 +528,8 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
     a.vals_out = d.v;
     a.ex = expand_args(b);
     a.hist = at<uint32_t>(b.ws, b.L.hist) + p * kRadixMax;
+    a.hist_copies = kHistCopies;
+    a.hist_stride = 4 * kRadixMax;
     a.status = at<uint64_t>(b.ws, b.L.sort_status) + static_cast<uint64_t>(p) * b.L.nsort_tiles_cap * (1u << RB);
     a.n = npairs;
     a.n_from_ctl = 1;  // the pass reads NO from the control block
@@ -959,6 +961,8 @@ int sort_arrays_rb(uint32_t* keys, uint32_t* vals, uint32_t* ka, uint32_t* va, u
     a.keys_out = dst_k;
     a.vals_out = dst_v;
     a.hist = at<uint32_t>(ws, L.hist) + p * kRadixMax;
+    a.hist_copies = 1;
+    a.hist_stride = 0;
     a.status = at<uint64_t>(ws, L.status) + p * stride;
     a.n = n;
     a.n_from_ctl = 0;

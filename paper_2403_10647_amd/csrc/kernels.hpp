@@ -502,6 +502,8 @@ GB_DEV uint32_t expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs,
 // ---------------------------------------------------------------------------
 // Radix sort plan: up to 4 passes over the low `bits` bits of the key.
 // ---------------------------------------------------------------------------
+constexpr int kHistCopies = 16;   // global copies of the digit histograms (see flush_hist)
+
 struct SortPlan {
   uint32_t passes;
   uint32_t shift[4];
@@ -587,13 +589,17 @@ GB_DEV void store_tile(const ExpandOutArgs& a, uint32_t tile, uint32_t n, const 
   if constexpr (RB > 0) hist_runs<Block, K, RB>(a.plan, keys, n, s_hist);
 }
 
+// A block's histograms go into one of kHistCopies global copies (chosen by
+// block index), so the blocks that finish together do not all add into the
+// same words; the first tile of each radix pass sums the copies.
 template <int RB, int Block>
-GB_DEV void flush_hist(const ExpandOutArgs& a, const uint32_t* s_hist) {
+GB_DEV void flush_hist(const SortPlan& plan, uint32_t* hist, const uint32_t* s_hist) {
   constexpr int R = 1 << RB;
+  uint32_t* h = hist + (blockIdx.x % kHistCopies) * (4 * kRadixMax);
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < a.plan.passes * R; i += Block) {
+  for (uint32_t i = threadIdx.x; i < plan.passes * R; i += Block) {
     const uint32_t v = s_hist[i];
-    if (v) atomicAdd(&a.hist[(i / R) * kRadixMax + (i % R)], v);
+    if (v) atomicAdd(&h[(i / R) * kRadixMax + (i % R)], v);
   }
 }
 
@@ -628,7 +634,7 @@ __global__ __launch_bounds__(Block, 4) void expand_kernel(ExpandOutArgs a) {
         expand_tile<Block, K, Batched, kBlocked, true>(a.ex, tile, npairs, ntiles, s_owner, s_wtot, keys, vals);
     store_tile<Block, K, RB>(a, tile, n, keys, vals, s_hist);
   }
-  if constexpr (RB > 0) flush_hist<RB, Block>(a, s_hist);
+  if constexpr (RB > 0) flush_hist<RB, Block>(a.plan, a.hist, s_hist);
 }
 
 // Batched builds: the tiles whose objects lie in more than one grid (about
@@ -654,7 +660,7 @@ __global__ __launch_bounds__(Block, 2) void expand_straddle_kernel(ExpandOutArgs
         expand_tile<Block, K, true, kBlocked, false>(a.ex, tile, npairs, ntiles, s_owner, s_wtot, keys, vals);
     store_tile<Block, K, RB>(a, tile, n, keys, vals, s_hist);
   }
-  if constexpr (RB > 0) flush_hist<RB, Block>(a, s_hist);
+  if constexpr (RB > 0) flush_hist<RB, Block>(a.plan, a.hist, s_hist);
 }
 
 // One read of the keys (regenerated from the expansion) for the digit
@@ -690,11 +696,7 @@ __global__ __launch_bounds__(Block) void hist_kernel(HistArgs a) {
     const uint32_t n = expand_tile<Block, K, Batched, kBlocked>(a.ex, tile, npairs, ntiles, s_owner, s_wtot, keys, vals);
     hist_runs<Block, K, RB>(a.plan, keys, n, s_hist);
   }
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < a.plan.passes * R; i += Block) {
-    const uint32_t v = s_hist[i];
-    if (v) atomicAdd(&a.hist[(i / R) * kRadixMax + (i % R)], v);
-  }
+  flush_hist<RB, Block>(a.plan, a.hist, s_hist);
 }
 
 }  // namespace gb

@@ -22,6 +22,8 @@ struct SortPassArgs {
   uint64_t* status;         // [ntiles][radix] look-back words (zeroed)
   uint64_t n;               // pairs, when not read from the control block
   uint32_t n_from_ctl;      // 1: n = ctl->npairs
+  uint32_t hist_copies;     // the pass's digit histogram is the sum of this many copies ...
+  uint32_t hist_stride;     // ... hist_stride words apart
   uint32_t shift;
   uint32_t width;           // digit width of this pass (<= RB)
   uint32_t counter;         // tile-counter slot
@@ -198,7 +200,10 @@ __global__ __launch_bounds__(Block, Source == kFromArrays ? 4 : 2) void onesweep
 #pragma unroll
       for (int j = 0; j < DPT; ++j) {
         const uint32_t d = tid * DPT + j;
-        hv[j] = d < static_cast<uint32_t>(R) ? a.hist[d] : 0u;
+        uint32_t h = 0;
+        if (d < static_cast<uint32_t>(R))
+          for (uint32_t c = 0; c < a.hist_copies; ++c) h += a.hist[c * a.hist_stride + d];
+        hv[j] = h;
         hsum += hv[j];
       }
       uint32_t htot;
