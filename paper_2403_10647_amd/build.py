@@ -45,6 +45,27 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+C_CHECK_SRC = os.path.join(ROOT, "tests", "c_abi", "check_build.c")
+C_CHECK_BIN = os.path.join(ROOT, "tests", "c_abi", "check_build")
+
+
+def build_c_check(verbose: bool = False) -> str:
+    """A plain C caller of the library (tests/c_abi): gridbuild.h and the HIP
+    runtime API only, compiled by the host C compiler and linked to the built
+    library, to show the boundary needs neither Python nor torch."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-D__HIP_PLATFORM_AMD__",
+           f"-I{os.path.join(rocm, 'include')}", f"-I{os.path.join(ROOT, 'include')}",
+           C_CHECK_SRC, "-o", C_CHECK_BIN, f"-L{HERE}", "-lgridbuild", f"-L{os.path.join(rocm, 'lib')}",
+           "-lamdhip64", "-lm", "-Wl,-rpath,$ORIGIN/../../paper_2403_10647_amd",
+           f"-Wl,-rpath,{os.path.join(rocm, 'lib')}"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    return C_CHECK_BIN
+
+
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)
+    build_c_check(verbose="-v" in sys.argv)
     print(LIB)
