@@ -270,7 +270,8 @@ class PlainBuild:
 
     For repeated builds of the same buffers (frames of a scene, benchmarks):
     each call is one C call.  The input tensors, the outputs and the workspace
-    must stay alive and in place while the object is used."""
+    must stay alive and in place while the object is used: a workspace that
+    later grows for another build moves, so size it first for all its users."""
 
     def __init__(self, g: GridInput, out: GridResult, ws: Optional[Workspace] = None, stream=None):
         self.g, self.out = g, out
@@ -305,23 +306,44 @@ def expand(g: GridInput, ws: Optional[Workspace] = None, stream=None):
     return cells[:no], objs[:no]
 
 
+def _desc_dtype() -> np.dtype:
+    """numpy view of grid_desc (same offsets), to fill descriptor arrays by column."""
+    o = grid_desc.out.offset
+    names = ["verts_soa", "tris", "nverts", "ntris", "lo", "hi", "res", "cells", "objs", "ranges", "cap_pairs", "npairs"]
+    formats = ["<u8", "<u8", "<u4", "<u4", ("<f4", 3), ("<f4", 3), ("<u4", 3), "<u8", "<u8", "<u8", "<u8", "<u8"]
+    offsets = [grid_desc.verts_soa.offset, grid_desc.tris.offset, grid_desc.nverts.offset, grid_desc.ntris.offset,
+               grid_desc.lo.offset, grid_desc.hi.offset, grid_desc.res.offset, o + grid_out.cells.offset,
+               o + grid_out.objs.offset, o + grid_out.ranges.offset, o + grid_out.cap_pairs.offset,
+               o + grid_out.npairs.offset]
+    return np.dtype({"names": names, "formats": formats, "offsets": offsets, "itemsize": C.sizeof(grid_desc)})
+
+
+_DESC_DTYPE = _desc_dtype()
+
+
+def _desc_view(arr) -> np.ndarray:
+    return np.frombuffer((C.c_char * C.sizeof(arr)).from_buffer(arr), dtype=_DESC_DTYPE)
+
+
 def _descs(inputs: List[GridInput], outs: Optional[List[GridResult]] = None):
-    arr = (grid_desc * len(inputs))()
-    for i, g in enumerate(inputs):
-        d = arr[i]
-        d.verts_soa = g.verts.data_ptr()
-        d.tris = g.tris.data_ptr()
-        d.nverts = g.nverts
-        d.ntris = g.ntris
-        d.lo[:] = [float(x) for x in g.lo]
-        d.hi[:] = [float(x) for x in g.hi]
-        d.res[:] = [int(x) for x in g.res]
-        if outs is not None:
-            o = outs[i]
-            d.out.cells = o.cells.data_ptr()
-            d.out.objs = o.objs.data_ptr()
-            d.out.ranges = o.ranges.data_ptr()
-            d.out.cap_pairs = int(o.cells.numel())
+    """ctypes array of grid_desc for the inputs (and outputs), filled column by column."""
+    n = len(inputs)
+    arr = (grid_desc * n)()
+    if n == 0:
+        return arr
+    a = _desc_view(arr)
+    a["verts_soa"] = [g.verts.data_ptr() for g in inputs]
+    a["tris"] = [g.tris.data_ptr() for g in inputs]
+    a["nverts"] = [g.nverts for g in inputs]
+    a["ntris"] = [g.ntris for g in inputs]
+    a["lo"] = np.asarray([g.lo for g in inputs], np.float32)
+    a["hi"] = np.asarray([g.hi for g in inputs], np.float32)
+    a["res"] = np.asarray([g.res for g in inputs], np.uint32)
+    if outs is not None:
+        a["cells"] = [o.cells.data_ptr() for o in outs]
+        a["objs"] = [o.objs.data_ptr() for o in outs]
+        a["ranges"] = [o.ranges.data_ptr() for o in outs]
+        a["cap_pairs"] = [o.cells.numel() for o in outs]
     return arr
 
 
@@ -332,7 +354,7 @@ def count_batched(inputs: List[GridInput], ws: Optional[Workspace] = None, strea
     wp, wn = ws.ptr_size(L.grid_workspace_size_batched(arr, len(inputs)))
     st = L.grid_count_batched(arr, len(inputs), wp, wn, _stream(stream))
     _check(st, "grid_count_batched")
-    return [int(arr[i].out.npairs) for i in range(len(inputs))]
+    return _desc_view(arr)["npairs"].tolist()
 
 
 def alloc_results(inputs: List[GridInput], caps: List[int]) -> List[GridResult]:
@@ -352,10 +374,34 @@ def build_batched(inputs: List[GridInput], outs: Optional[List[GridResult]] = No
     arr = _descs(inputs, outs)
     wp, wn = ws.ptr_size(L.grid_workspace_size_batched(arr, len(inputs)))
     st = L.grid_build_batched(arr, len(inputs), wp, wn, _stream(stream))
-    for i, o in enumerate(outs):
-        o.npairs = int(arr[i].out.npairs)
+    for o, n in zip(outs, _desc_view(arr)["npairs"].tolist()):
+        o.npairs = n
     _check(st, "grid_build_batched")
     return outs
+
+
+class BatchedBuild:
+    """grid_build_batched of fixed inputs into fixed outputs, descriptors marshalled once.
+
+    For repeated batched builds of the same buffers; each call is one C call.
+    The tensors and the workspace must stay alive and in place while it is used
+    (a workspace that later grows for another build moves)."""
+
+    def __init__(self, inputs: List[GridInput], outs: List[GridResult], ws: Optional[Workspace] = None, stream=None):
+        self.inputs, self.outs = inputs, outs
+        self.ws = ws or default_workspace(inputs[0].verts.device)
+        self._arr = _descs(inputs, outs)
+        self._view = _desc_view(self._arr)
+        wp, wn = self.ws.ptr_size(lib().grid_workspace_size_batched(self._arr, len(inputs)))
+        self._fn = lib().grid_build_batched
+        self._args = (self._arr, len(inputs), wp, wn, _stream(stream))
+
+    def __call__(self) -> List[GridResult]:
+        st = self._fn(*self._args)
+        for o, n in zip(self.outs, self._view["npairs"].tolist()):
+            o.npairs = n
+        _check(st, "grid_build_batched")
+        return self.outs
 
 
 def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, nbits: int, ws: Optional[Workspace] = None, stream=None):

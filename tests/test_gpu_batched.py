@@ -141,3 +141,23 @@ def test_batched_under_tuning(G, fused, digit, shape):
         G.tune_set("fused_expand", 0)
         G.tune_set("max_digit_bits", 9)
         G.tune_set("sort_shape", 3)
+
+
+def test_batched_build_object_repeats(G):
+    # marshalled once, called again and again: the same grids as build_batched and the oracle
+    batch = _uneven_batch()[:8]
+    inputs = [G.GridInput.from_scene(s) for s in batch]
+    ref = G.build_batched(inputs)
+    outs = G.alloc_results(inputs, [r.npairs for r in ref])
+    b = G.BatchedBuild(inputs, outs)
+    for _ in range(3):
+        for o in outs:
+            o.cells.fill_(0)
+        b()
+        for o, r in zip(outs, ref):
+            assert o.npairs == r.npairs
+            assert torch.equal(o.cells[:o.npairs], r.cells[:r.npairs])
+            assert torch.equal(o.objs[:o.npairs], r.objs[:r.npairs])
+            assert torch.equal(o.ranges, r.ranges)
+    for o, s in zip(outs, batch):
+        _cmp_oracle(o, s)
