@@ -65,6 +65,25 @@ def test_batched_uneven_matches_oracle(G):
         _cmp_oracle(r, s)
 
 
+def test_batched_tiles_over_two_grids(G):
+    # count tiles (8192 triangles) that hold triangles of exactly two grids,
+    # with and without empty grids between them, and tiles over three
+    sizes = [6000, 0, 0, 6000, 3000, 9000, 0, 100, 8000, 200, 0]
+    batch = scenes.make_batch(6, ngrids=len(sizes), sizes=np.asarray(sizes))
+    for s in batch:
+        if s.ntris == 0:
+            s.lo = np.zeros(3, np.float32)
+            s.hi = np.ones(3, np.float32)
+            s.res = np.asarray([2, 3, 4], np.uint32)
+    _say("build_batched two-grid tiles", sizes)
+    inputs = [G.GridInput.from_scene(s) for s in batch]
+    caps = G.count_batched(inputs)
+    res = G.build_batched(inputs)
+    for s, n, r in zip(batch, caps, res):
+        assert n == r.npairs, s.name
+        _cmp_oracle(r, s)
+
+
 def test_batched_equals_plain_on_512_grids(G):
     batch = scenes.make_batch(0, ngrids=512)
     _say("build_batched 512", sum(s.ntris for s in batch))
