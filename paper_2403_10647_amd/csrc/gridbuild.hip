@@ -592,7 +592,8 @@ int launch_ranges(Build& b, uint64_t merge_items_cap) {
   GB_LAUNCHED();
   }
   TraceScope ts(b.s, "ranges");
-  ranges_kernel<kRangesBlock, kRangesK, B><<<persistent_blocks(tiles, 8), kRangesBlock, 0, b.s>>>(a);
+  auto kern = ranges_kernel<kRangesBlock, kRangesK, B>;
+  kern<<<resident_blocks(kern, kRangesBlock, tiles), kRangesBlock, 0, b.s>>>(a);
   GB_LAUNCHED();
   return GRID_OK;
 }

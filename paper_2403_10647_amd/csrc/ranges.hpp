@@ -193,8 +193,11 @@ __global__ __launch_bounds__(Block) void split_kernel(RangesArgs a) {
   }
 }
 
+// Eight waves per SIMD: every block of the persistent grid is resident at once
+// (a block that started late would run its whole static share of the tiles
+// after the others had finished).
 template <int Block, int K, bool Batched>
-__global__ __launch_bounds__(Block) void ranges_kernel(RangesArgs a) {
+__global__ __launch_bounds__(Block, 8) void ranges_kernel(RangesArgs a) {
   constexpr int D = Block * K;
   static_assert(D < 65535, "tile-relative cells and pair offsets are held in 16 bits");
   // Within a tile the pairs' cells lie in [i0 - 1, i1 - 1] and the begins in
