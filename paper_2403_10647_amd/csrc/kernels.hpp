@@ -40,21 +40,6 @@ GB_DEV uint32_t grid_of_tri(const GridSet& s, uint32_t t, uint32_t g) {
   }
 }
 
-// First grid whose triangle range contains t (binary search over the table).
-template <bool Batched>
-GB_DEV uint32_t grid_search(const GridSet& s, uint32_t t) {
-  if constexpr (Batched) {
-    uint32_t lo = 0, hi = s.ngrids;  // answer in [lo, hi)
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (s.table[mid].tri_base <= t) lo = mid; else hi = mid;
-    }
-    return lo;
-  } else {
-    return 0;
-  }
-}
-
 // The look-back words the radix passes will use, cleared by the kernel that
 // runs before them: pass p uses ceil(NO / tile[p]) * radix[p] words from
 // status + p * stride.
@@ -119,9 +104,9 @@ enum CountMode : int { kCountPlain = 0, kCountOneGrid = 1, kCountPerItem = 2 };
 // CountCells for the tile's triangles base + k * Block + tid: writes each box
 // and leaves the counts in s_val (striped order).
 template <int Block, int K, int Mode>
-GB_DEV void count_items(const CountArgs& a, const GridDev& G0, uint64_t base, uint32_t* s_val) {
+GB_DEV void count_items(const CountArgs& a, const GridDev& G0, uint64_t base, uint32_t* s_val, uint32_t g0 = 0) {
   const uint32_t tid = threadIdx.x;
-  uint32_t g = Mode == kCountPerItem ? grid_search<true>(a.gs, static_cast<uint32_t>(base)) : 0;
+  uint32_t g = g0;  // kCountPerItem: the grid of the tile's first triangle, walked forward per item
 
   // all index loads, then all vertex loads, then the arithmetic
   uint32_t gi[K], idx[K][3];
@@ -191,18 +176,21 @@ __global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
   const uint32_t tid = threadIdx.x;
   const uint64_t base = static_cast<uint64_t>(tile) * Tile;
   const uint32_t ntiles = (a.ntris + Tile - 1) / Tile;
+  // batched: the grid of the tile's first triangle, and whether every
+  // triangle of the tile lies in it (the same for the whole workgroup)
+  uint32_t gl = 0;
+  bool one = true;
   if constexpr (Batched) {
-    // the tile is the same for the whole workgroup, and so are its grids
     const uint32_t t0 = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(base < a.ntris ? base : a.ntris - 1));
     const uint64_t e = base + Tile < a.ntris ? base + Tile : a.ntris;
     const uint32_t t1 = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(e - 1));
-    const uint32_t gl = __builtin_amdgcn_readfirstlane(grid_of_tri_wave(a.gs, t0));
-    const bool one = gl + 1 >= a.gs.ngrids || a.gs.table[gl + 1].tri_base > t1;
+    gl = __builtin_amdgcn_readfirstlane(grid_of_tri_wave(a.gs, t0));
+    one = gl + 1 >= a.gs.ngrids || a.gs.table[gl + 1].tri_base > t1;
     if (one) {
       const GridDev G = a.gs.table[gl];
       count_items<Block, K, kCountOneGrid>(a, G, base, s_val);
     } else {
-      count_items<Block, K, kCountPerItem>(a, a.gs.table[gl], base, s_val);
+      count_items<Block, K, kCountPerItem>(a, a.gs.table[gl], base, s_val, gl);
     }
   } else {
     count_items<Block, K, kCountPlain>(a, a.gs.one, base, s_val);
@@ -238,7 +226,9 @@ __global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
       uint64_t j = (excl + tmask) >> a.tile_shift;
       const uint64_t jlast = (excl + mine[k] - 1) >> a.tile_shift;
       if (j <= jlast && j < a.ntfo) {
-        const uint32_t g = grid_search<Batched>(a.gs, static_cast<uint32_t>(t));  // rare: about one object per tile
+        // about one object per expansion tile; its grid is the tile's first
+        // or one a few entries after it
+        const uint32_t g = one ? gl : grid_of_tri<Batched>(a.gs, static_cast<uint32_t>(t), gl);
         for (; j <= jlast && j < a.ntfo; ++j) {
           a.tfo[j] = static_cast<uint32_t>(t);
           if constexpr (Batched) a.tfg[j] = g;
