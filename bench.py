@@ -33,7 +33,9 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 
 def kernel_bytes(name: str, T: int, NO: int, R: int) -> float:
-    """Algorithmic bytes one launch of `name` must move (see the design doc for the model)."""
+    """Algorithmic bytes one launch of `name` must move: each input read once and
+    each output written once, for T triangles, NO pairs and R cells (look-back
+    words, histograms and re-reads are not counted)."""
     return {
         "count_scan": 60.0 * T,            # 12 B indices + 36 B vertices in, 4 B start + 8 B box out
         "expand_hist": 12.0 * T + 8.0 * NO,  # start + box in, object-order pairs out
