@@ -195,6 +195,51 @@ def run_batched(G, args) -> dict:
     return res, inputs, outs_p
 
 
+def run_ablation(G, args, gin, out, ws, reps: int = 5) -> dict:
+    """Pair generation one thread per pair (the per-pair expansion of the
+    paper's method) against one thread per object (the MakePairs of sorted-grid
+    builders), with the same sort and ranges after it, on the headline scene and
+    on the 1M mixed scene whose 5% large triangles hold most of its pairs.
+    Outputs are compared bit for bit with the default build's."""
+    import torch
+    from paper_2403_10647_amd import scenes
+    mixed = G.GridInput.from_scene(scenes.make_scene("mixed", seed=args.seed))
+    n_mixed, _ = G.count(mixed, ws)
+    cases = [(args.workload, gin, out), ("mixed", mixed, G.build(mixed, cap_pairs=n_mixed, ws=ws))]
+    res = {}
+    for name, g, ref in cases:
+        n = ref.npairs
+        row = {"triangles": g.ntris, "npairs": n}
+        for knob, label, gen in ((0, "per_pair", "expand_hist"), (1, "per_object", "makepairs_hist")):
+            G.tune_set("per_object_pairs", knob)
+            try:
+                o = G.build(g, cap_pairs=n, ws=ws)
+                run = G.PlainBuild(g, o, ws)
+                run()
+                torch.cuda.synchronize()
+                G.trace_enable(True)
+                G.trace_read()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    run()
+                torch.cuda.synchronize()
+                wall = (time.perf_counter() - t0) * 1e3 / reps
+                k = G.trace_read()
+            finally:
+                G.trace_enable(False)
+                G.tune_set("per_object_pairs", 0)
+            same = (torch.equal(o.cells[:n], ref.cells[:n]) and torch.equal(o.objs[:n], ref.objs[:n])
+                    and torch.equal(o.ranges, ref.ranges))
+            row[label] = {"ms_per_build": round(wall, 4),
+                          "pair_generation_ms": round(k[gen][1] / k[gen][0], 4) if gen in k else None,
+                          "identical_to_default": bool(same)}
+            del o, run
+        a, b = row["per_pair"]["pair_generation_ms"], row["per_object"]["pair_generation_ms"]
+        row["per_object_over_per_pair"] = round(b / a, 2) if a and b else None
+        res[name] = row
+    return res
+
+
 def run_served(G, args, pool, pool_refs, big, big_ref) -> dict:
     """Poisson arrivals of requests drawn from the batch's grids plus the 10M-triangle scene once a
     second, through the continuous-batching server; every output is compared on the device with the
@@ -245,6 +290,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-grid batched build and serving")
     ap.add_argument("--no-serve", action="store_true", help="skip serving")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the per-object pair generation comparison")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-budget-gb", type=int, default=64)
@@ -381,6 +428,9 @@ def main():
             print("# serving", file=sys.stderr, flush=True)
             result["served"] = run_served(G, args, pool, pool_refs, gin, out)
         del pool, pool_refs
+    if not args.no_ablation:
+        print("# per-object pair generation", file=sys.stderr, flush=True)
+        result["ablation"] = run_ablation(G, args, gin, out, ws)
     if not args.no_cpu_baseline:
         print("# cpu baseline", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(scene, out)

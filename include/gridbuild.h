@@ -193,6 +193,14 @@ int grid_scan_u32(const uint32_t *in, const uint32_t *flags, uint32_t *out, uint
  *   "sort_shape"      workgroup shape of radix passes that read arrays:
  *                     0 = 512 threads x 16 pairs, 1 = 256 x 16, 2 = 1024 x 8,
  *                     3 = 1024 x 16 (default), 4 = 1024 x 15
+ *   "per_object_pairs" 1: plain builds generate their pairs with one thread per
+ *                     object, each writing all of its object's pairs (the
+ *                     sorted-grid pair generation of the Related Work
+ *                     section, whose MakePairs kernel the Test Results section
+ *                     finds dominant on architectural scenes); 0 (default):
+ *                     one thread per pair (Section 3), equal work
+ *                     whatever an object's size.  Ignored by batched builds and
+ *                     while "fused_expand" is 1.
  * Outputs never depend on the knobs.  GRID_E_INVAL for an unknown key or value. */
 int grid_tune_set(const char *key, int value);
 int grid_tune_get(const char *key, int *value);
@@ -207,7 +215,8 @@ int grid_sort_plan(uint32_t nbits, uint32_t *passes, uint32_t widths[4], uint32_
 /* Per-kernel totals collected while tracing is on. */
 typedef struct grid_trace_entry {
   char name[48];       /* kernel: zero, count_scan, plan, sink, expand_hist, expand_straddle, hist,
-                          onesweep_expand, onesweep, onesweep_grids, split, ranges */
+                          makepairs_hist, onesweep_expand, onesweep, onesweep_grids, split,
+                          ranges */
   uint32_t launches;   /* launches since the last read */
   double total_ms;     /* summed event-measured duration */
 } grid_trace_entry;

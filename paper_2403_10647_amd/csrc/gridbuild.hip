@@ -30,6 +30,7 @@ constexpr int kSortTileMin = 4096;                      // smallest tile of any 
 constexpr int kRangesBlock = 256, kRangesK = 16;        // 4096 merge items per range tile
 constexpr int kMergeTile = kRangesBlock * kRangesK;
 constexpr int kScanBlock = 256, kScanK = 8;
+constexpr int kMakePairsBlock = 256;                    // per-object pair generation: one thread per object
 constexpr int kPlanBlock = 1024;
 constexpr int kMaxRadixBits = 11;
 constexpr int kKeyMapBits = 13;                         // batched key map: at most 8192 buckets
@@ -131,6 +132,10 @@ struct Plan {
 // expansion writes the object-order pairs and every pass reads arrays.
 int g_max_digit_bits = 9;
 int g_fused_expand = 0;
+// Plain builds only, and only while the first radix pass reads arrays: 1 makes
+// one thread per object write all of that object's pairs (the sorted-grid
+// style the paper measures its per-pair expansion against), for comparison.
+int g_per_object_pairs = 0;
 int g_sort_shape = 3;  // radix passes from arrays: 0 = 512 x 16, 1 = 256 x 16, 2 = 1024 x 8, 3 = 1024 x 16,
                        // 4 = 1024 x 15
 
@@ -381,6 +386,15 @@ int launch_expand(Build& b, uint32_t* cells, uint32_t* objs, uint64_t npairs) {
   a.clear = status_clear(b, RB);
   a.vec16 = ((reinterpret_cast<uintptr_t>(cells) | reinterpret_cast<uintptr_t>(objs)) & 15u) == 0;
   a.ctl = at<Control>(b.ws, b.L.ctl);
+  if constexpr (!B) {
+    if (g_per_object_pairs) {
+      TraceScope ts(b.s, RB > 0 ? "makepairs_hist" : "makepairs");
+      const uint32_t blocks = static_cast<uint32_t>(std::max<uint64_t>(1, ceil_div(b.ntris, kMakePairsBlock)));
+      makepairs_kernel<kMakePairsBlock, RB><<<blocks, kMakePairsBlock, 0, b.s>>>(a);  // one thread per object
+      GB_LAUNCHED();
+      return GRID_OK;
+    }
+  }
   {
     TraceScope ts(b.s, RB > 0 ? "expand_hist" : "expand");
     auto kern = expand_kernel<kExpandBlock, kExpandK, RB, B>;
@@ -1136,6 +1150,11 @@ int grid_tune_set(const char* key, int value) {
     g_sort_shape = value;
     return GRID_OK;
   }
+  if (std::strcmp(key, "per_object_pairs") == 0) {
+    if (value != 0 && value != 1) return GRID_E_INVAL;
+    g_per_object_pairs = value;
+    return GRID_OK;
+  }
   return GRID_E_INVAL;
 }
 
@@ -1154,6 +1173,7 @@ int grid_tune_get(const char* key, int* value) {
   if (std::strcmp(key, "max_digit_bits") == 0) { *value = g_max_digit_bits; return GRID_OK; }
   if (std::strcmp(key, "fused_expand") == 0) { *value = g_fused_expand; return GRID_OK; }
   if (std::strcmp(key, "sort_shape") == 0) { *value = g_sort_shape; return GRID_OK; }
+  if (std::strcmp(key, "per_object_pairs") == 0) { *value = g_per_object_pairs; return GRID_OK; }
   return GRID_E_INVAL;
 }
 

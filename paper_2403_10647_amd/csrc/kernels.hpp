@@ -653,6 +653,67 @@ __global__ __launch_bounds__(Block, 2) void expand_straddle_kernel(ExpandOutArgs
   if constexpr (RB > 0) flush_hist<RB, Block>(a.plan, a.hist, s_hist);
 }
 
+// The pair generation of sorted-grid builders (Related Work; their MakePairs
+// kernel, which the Test Results section finds dominant on architectural
+// scenes): one thread per object writes all of that object's pairs, so a
+// thread's work is its object's cell count.  Plain builds only; it writes
+// what expand_kernel writes: the object-order pairs, the digit histograms of
+// every radix pass and the passes' cleared look-back words.
+template <int Block, int RB>
+__global__ __launch_bounds__(Block) void makepairs_kernel(ExpandOutArgs a) {
+  constexpr int R = RB > 0 ? 1 << RB : 1;
+  __shared__ uint32_t s_hist[RB > 0 ? 4 * R : 1];
+  if (build_failed(a.ctl)) return;
+  if constexpr (RB > 0) {
+    clear_status<Block>(a.clear, a.ctl->npairs);
+    for (int i = threadIdx.x; i < 4 * R; i += Block) s_hist[i] = 0;
+    __syncthreads();
+  }
+  const uint32_t res0 = a.ex.gs.one.res[0];
+  const uint32_t res01 = res0 * a.ex.gs.one.res[1];
+  // a run of equal digits per pass is added to the histogram once
+  uint32_t cur[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};
+  const uint64_t step = static_cast<uint64_t>(gridDim.x) * Block;
+  for (uint64_t t = static_cast<uint64_t>(blockIdx.x) * Block + threadIdx.x; t < a.ex.ntris; t += step) {
+    const Box b = unpack_box(a.ex.box[t]);
+    const uint64_t s0 = a.ex.start[t];
+    const uint32_t n = b.m[0] * b.m[1] * b.m[2];
+    uint32_t x = 0, y = 0, z = 0;  // GlobalCoords stepped along the object's cells
+    for (uint32_t r = 0; r < n; ++r) {
+      const uint32_t cell = (b.lo[0] + x) + res0 * (b.lo[1] + y) + res01 * (b.lo[2] + z);
+      a.cells[s0 + r] = cell;
+      a.objs[s0 + r] = static_cast<uint32_t>(t);
+      if constexpr (RB > 0) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          if (static_cast<uint32_t>(p) < a.plan.passes) {
+            const uint32_t d = (cell >> a.plan.shift[p]) & ((1u << a.plan.width[p]) - 1u);
+            if (cnt[p] != 0 && d != cur[p]) {
+              atomicAdd(&s_hist[p * R + cur[p]], cnt[p]);
+              cnt[p] = 0;
+            }
+            cur[p] = d;
+            ++cnt[p];
+          }
+        }
+      }
+      if (++x == b.m[0]) {
+        x = 0;
+        if (++y == b.m[1]) {
+          y = 0;
+          ++z;
+        }
+      }
+    }
+  }
+  if constexpr (RB > 0) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+      if (cnt[p] != 0) atomicAdd(&s_hist[p * R + cur[p]], cnt[p]);
+    flush_hist<RB, Block>(a.plan, a.hist, s_hist);
+  }
+}
+
 // One read of the keys (regenerated from the expansion) for the digit
 // histograms of every pass; also clears the look-back words of every pass.
 struct HistArgs {

@@ -167,4 +167,7 @@ def test_tune_rejects_bad_values(G):
         G.tune_set("max_digit_bits", 12)
     with pytest.raises(G.GridError):
         G.tune_set("no_such_knob", 1)
+    with pytest.raises(G.GridError):
+        G.tune_set("per_object_pairs", 2)
     assert G.tune_get("max_digit_bits") == 9 and G.tune_get("fused_expand") in (0, 1)
+    assert G.tune_get("per_object_pairs") == 0
