@@ -214,9 +214,9 @@ int grid_sort_plan(uint32_t nbits, uint32_t *passes, uint32_t widths[4], uint32_
 
 /* Per-kernel totals collected while tracing is on. */
 typedef struct grid_trace_entry {
-  char name[48];       /* kernel: zero, count_scan, plan, sink, expand_hist, expand_straddle, hist,
-                          makepairs_hist, onesweep_expand, onesweep, onesweep_grids, split,
-                          ranges */
+  char name[48];       /* kernel: zero, count_scan, plan, sink, expand, expand_hist, expand_straddle,
+                          hist, makepairs, makepairs_hist, onesweep_expand, onesweep,
+                          onesweep_grids, split, ranges */
   uint32_t launches;   /* launches since the last read */
   double total_ms;     /* summed event-measured duration */
 } grid_trace_entry;
