@@ -224,12 +224,14 @@ __global__ __launch_bounds__(Block, 8) void ranges_kernel(RangesArgs a) {
     const uint64_t i0 = d0 - j0, i1 = d1 - j1;
     const uint32_t np = static_cast<uint32_t>(j1 - j0), ne = static_cast<uint32_t>(i1 - i0);
     const uint32_t cbase = static_cast<uint32_t>(i0) - 1u;  // cells of the tile's pairs are >= i0 - 1
-    // all K loads of a thread in flight at once (np <= D = Block * K)
+    // all K loads of a thread in flight at once (np <= D = Block * K), at
+    // 32-bit offsets from the tile's first pair
+    const uint32_t* cells_t = gd.out_cells + j0;
     uint32_t cv[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const uint32_t p = k * Block + tid;
-      cv[k] = p < np ? gd.out_cells[j0 + p] : 0u;
+      cv[k] = p < np ? cells_t[p] : 0u;
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -260,15 +262,34 @@ __global__ __launch_bounds__(Block, 8) void ranges_kernel(RangesArgs a) {
       }
     }
     __syncthreads();
-    // ranges[q] for q in [2 i0 - 1, 2 i1 - 1): q = 2c is begin(c), q = 2c - 1 is end(c - 1) = begin(c)
+    // ranges[q] for q in [2 i0 - 1, 2 i1 - 1): q = 2c is begin(c), q = 2c - 1 is end(c - 1) = begin(c).
+    // (i1 >= 1: the first merged item is event 0.)  Entry q0 + ql is the
+    // begin of cell i0 + (ql + odd) / 2, with odd = 1 only for the first tile
+    // (q0 = 0); at most 2 * D entries per tile, at 32-bit offsets from q0.
     const uint64_t q0 = i0 > 0 ? 2 * i0 - 1 : 0;
     const uint64_t q1e = 2 * i1 - 1;
     const uint64_t q1 = q1e < 2 * ncell ? q1e : 2 * ncell;
-    // at most 2 * D table entries per tile
+    const uint32_t nq = static_cast<uint32_t>(q1 > q0 ? q1 - q0 : 0);
+    const uint32_t odd = i0 == 0 ? 1u : 0u;
+    const uint32_t jb = static_cast<uint32_t>(j0);
+    uint32_t* out_t = gd.out_ranges + q0;
+    // sixteen LDS reads in flight, then their stores (a read past the tile's
+    // entries is clamped into s_begin and stores nothing)
+    constexpr int kGroup = 16;
+    static_assert((2 * K) % kGroup == 0, "output entries are written in groups");
 #pragma unroll
-    for (int k = 0; k < 2 * K; ++k) {
-      const uint64_t q = q0 + static_cast<uint64_t>(k) * Block + tid;
-      if (q < q1) gd.out_ranges[q] = static_cast<uint32_t>(j0) + s_begin[(q + 1) / 2 - i0];
+    for (int k0 = 0; k0 < 2 * K; k0 += kGroup) {
+      uint32_t v[kGroup];
+#pragma unroll
+      for (int k = 0; k < kGroup; ++k) {
+        const uint32_t e = ((k0 + k) * Block + tid + odd) >> 1;
+        v[k] = s_begin[e < static_cast<uint32_t>(D) ? e : D - 1];
+      }
+#pragma unroll
+      for (int k = 0; k < kGroup; ++k) {
+        const uint32_t ql = (k0 + k) * Block + tid;
+        if (ql < nq) out_t[ql] = jb + v[k];
+      }
     }
     __syncthreads();
   }
