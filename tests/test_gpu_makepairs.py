@@ -97,3 +97,36 @@ def test_per_object_capacity_error(G, per_object):
         G.build(g, out=out)
     assert e.value.status == G.GRID_E_CAPACITY and out.npairs == n
     assert bool((out.cells == -7).all()) and bool((out.objs == -7).all()) and bool((out.ranges == -7).all())
+
+
+def test_per_object_four_radix_passes(G, per_object):
+    # 19 key bits at digits of at most 6 bits: four passes, every histogram run counter in use
+    s = scenes.make_scene("small", seed=11, ntris=20_000)
+    s.res = np.asarray([128, 64, 64], np.uint32)
+    G.tune_set("max_digit_bits", 6)
+    try:
+        passes = G.sort_plan(19)[0]
+        assert passes == 4
+        _check(G, s)
+    finally:
+        G.tune_set("max_digit_bits", 9)
+
+
+def test_per_object_knob_left_alone_elsewhere(G, per_object):
+    # batched builds always expand per pair, and a fused first pass regenerates
+    # its keys itself: both still give the oracle's grids with the knob set
+    batch = scenes.make_batch(12, ngrids=6, sizes=np.array([3000, 0, 12_000, 5, 9000, 700]))
+    for s in batch:
+        if s.ntris == 0:
+            s.lo, s.hi = np.zeros(3, np.float32), np.ones(3, np.float32)
+            s.res = np.asarray([3, 2, 5], np.uint32)
+    res = G.build_batched([G.GridInput.from_scene(s) for s in batch])
+    for r, s in zip(res, batch):
+        c, o, rg = r.numpy()
+        oc, oo, orr = oracle.build_scene(s)
+        assert np.array_equal(c, oc) and np.array_equal(o, oo) and np.array_equal(rg, orr), s.name
+    G.tune_set("fused_expand", 1)
+    try:
+        _check(G, scenes.make_scene("mixed", seed=13, ntris=30_000))
+    finally:
+        G.tune_set("fused_expand", 0)
