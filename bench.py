@@ -306,7 +306,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it (use --gpus 1)",
+        print("bench.py: runs on one GPU only; multi-GPU runs are not supported (use --gpus 1)",
               file=sys.stderr, flush=True)
         sys.exit(2)
 
