@@ -2,7 +2,8 @@
 
 Each case plants one mistake (a wrong index, a dropped term, a flipped sign, a
 swapped operand) into a private copy of the oracle's source, compiles it on the
-CPU, and checks that the brute-force and GlobalCoords pins reject it.  The
+CPU, and checks that the brute-force, GlobalCoords and FP32 cell-face pins
+reject it.  The
 oracle itself is never modified.
 """
 import ctypes as C
@@ -13,6 +14,7 @@ import subprocess
 import numpy as np
 import pytest
 
+import fp32_model
 import oracle
 from brute import brute_pairs, dyadic_scene
 
@@ -33,7 +35,19 @@ MUTATIONS = {
     "sort_descending": ("return cells[a] < cells[b];", "return cells[a] > cells[b];"),
     "ranges_begin_after_add": ("ranges[2 * c] = static_cast<uint32_t>(acc);\n    acc += per_cell[c];",
                                "acc += per_cell[c];\n    ranges[2 * c] = static_cast<uint32_t>(acc);"),
+    # the cell width w = (hi - lo) / res, and the map divides by it instead of multiplying by inv
+    "map_divides_by_cell_width": [("inv[a] = static_cast<float>(res[a]) / ext;", "inv[a] = ext / static_cast<float>(res[a]);"),
+                                  ("float u = s * inv;", "float u = s / inv;")],
+    # the subtraction and the product carried in double precision
+    "map_double_intermediate": ("float s = p - lo;\n  float u = s * inv;\n  float f = std::floor(u);",
+                                "double s = static_cast<double>(p) - lo;\n  double u = s * inv;\n"
+                                "  float f = static_cast<float>(std::floor(u));"),
 }
+
+
+def _edits(name):
+    m = MUTATIONS[name]
+    return m if isinstance(m, list) else [m]
 
 
 def _compile(tmp_path, name, src):
@@ -46,6 +60,8 @@ def _compile(tmp_path, name, src):
     L.oracle_build.argtypes = [P, C.c_uint32, P, C.c_uint32, P, P, P, P, P, P, C.c_uint64, P]
     L.oracle_build.restype = C.c_int
     L.oracle_global_coords.argtypes = [P, P, C.c_uint32, P]
+    L.oracle_count_cells.argtypes = [P, C.c_uint32, P, C.c_uint32, P, P, P, P, P, P]
+    L.oracle_count_cells.restype = C.c_int
     return L
 
 
@@ -53,8 +69,55 @@ def _p(a):
     return a.ctypes.data_as(C.c_void_p)
 
 
+def _face_cases():
+    """Degenerate triangles at and beside the cell faces of two non-dyadic grids,
+    with each corner's cell from the exact rational model of the FP32 map."""
+    cases = []
+    rng = np.random.default_rng(7)
+    for lo, hi, res in (((0.0, -3.7, 11.3), (17.219383, 41.9, 12.05), (112, 333, 77)),
+                        ((-51.4, 2.2, 0.1), (60.7, 9.3, 93.3), (1001, 71, 619))):
+        lo = np.asarray(lo, np.float32)
+        hi = np.asarray(hi, np.float32)
+        res = np.asarray(res, np.uint32)
+        pts = []
+        for a in range(3):
+            ks = rng.integers(0, int(res[a]) + 1, size=60)
+            p = np.asarray([float(lo[a]) + int(k) * (float(hi[a]) - float(lo[a])) / int(res[a]) for k in ks], np.float32)
+            up = np.nextafter(p, np.float32(np.inf))
+            dn = np.nextafter(p, np.float32(-np.inf))
+            pts.append(np.concatenate([p, up, dn]))
+        n = len(pts[0])
+        verts = np.ascontiguousarray(np.repeat(np.stack(pts), 3, axis=1), np.float32)   # 3 equal vertices each
+        tris = np.arange(3 * n, dtype=np.uint32).reshape(n, 3)
+        want = np.asarray([[fp32_model.cell_fp32(pts[a][t], lo[a], hi[a], int(res[a])) for a in range(3)]
+                           for t in range(n)], np.uint32)
+        cases.append((verts, tris, lo, hi, res, want))
+    return cases
+
+
+_FACE_CASES = None
+
+
+def _faces_pass(L) -> bool:
+    global _FACE_CASES
+    if _FACE_CASES is None:
+        _FACE_CASES = _face_cases()
+    for verts, tris, lo, hi, res, want in _FACE_CASES:
+        t = tris.shape[0]
+        box_lo = np.zeros((t, 3), np.uint32)
+        box_m = np.zeros((t, 3), np.uint32)
+        cnt = np.zeros(t, np.uint32)
+        st = L.oracle_count_cells(_p(verts), verts.shape[1], _p(tris), t, _p(lo), _p(hi), _p(res),
+                                  _p(box_lo), _p(box_m), _p(cnt))
+        if st != 0 or not np.array_equal(box_lo, want) or not (box_m == 1).all():
+            return False
+    return True
+
+
 def _pins_pass(L) -> bool:
-    """Run the brute-force and GlobalCoords pins against library L."""
+    """Run the brute-force, GlobalCoords and FP32 cell-face pins against library L."""
+    if not _faces_pass(L):
+        return False
     lo5 = np.array([5, 7, 11], np.uint32)
     for m in [(2, 3, 4), (3, 1, 2), (4, 4, 1)]:
         m = np.asarray(m, np.uint32)
@@ -117,7 +180,20 @@ def test_unmutated_copy_passes(tmp_path):
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_mutation_is_caught(tmp_path, name):
-    old, new = MUTATIONS[name]
-    assert SRC.count(old) == 1, f"mutation anchor for {name} not found exactly once"
+    src = SRC
+    for old, new in _edits(name):
+        assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"
+        src = src.replace(old, new)
     # a crash (e.g. a division by a zero extent) also counts as caught
-    assert _run_pins(tmp_path, name, SRC.replace(old, new)) != 0, f"planted mistake {name} was not caught"
+    assert _run_pins(tmp_path, name, src) != 0, f"planted mistake {name} was not caught"
+
+
+@pytest.mark.parametrize("name", ["map_divides_by_cell_width", "map_double_intermediate"])
+def test_fp32_mutation_survives_dyadic_pins(tmp_path, name):
+    # these two mistakes agree with exact arithmetic on dyadic inputs, so only the
+    # cell-face pins on non-dyadic grids can catch them: check that they do
+    src = SRC
+    for old, new in _edits(name):
+        src = src.replace(old, new)
+    L = _compile(tmp_path, name, src)
+    assert not _faces_pass(L)

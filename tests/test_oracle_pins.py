@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+import fp32_model
 from brute import brute_pairs, dyadic_scene
 from paper_2403_10647_amd import scenes
 
@@ -77,6 +78,100 @@ def test_nan_and_inf_coordinates():
     box_lo, box_m, count = oracle.count_cells(verts, tris, lo, hi, res)
     assert count.tolist() == [4, 1, 1, 8]
     assert box_lo[:, 0].tolist() == [2, 0, 0, 0]
+
+
+# --- the FP32 map on non-dyadic grids, against an exact rational model ----------------------
+
+def _face_points(rng, lo, hi, res, nface=24):
+    """Points at, and one or two ulps beside, the cell faces of one axis (plus random
+    points and the bounds themselves), as float32."""
+    pts = [lo, hi, np.nextafter(lo, np.float32(-np.inf)), np.nextafter(hi, np.float32(np.inf))]
+    for k in rng.integers(0, res + 1, size=nface):
+        p = np.float32(float(lo) + int(k) * (float(hi) - float(lo)) / int(res))
+        for step in range(-2, 3):
+            q = p
+            for _ in range(abs(step)):
+                q = np.nextafter(q, np.float32(np.inf if step > 0 else -np.inf))
+            pts.append(q)
+    pts += list(rng.uniform(float(lo), float(hi), size=8).astype(np.float32))
+    return np.asarray(pts, np.float32)
+
+
+def _non_dyadic_grid(rng):
+    lo = rng.uniform(-60, 60, size=3).astype(np.float32)
+    ext = rng.uniform(0.3, 150, size=3)
+    hi = (lo.astype(np.float64) + ext).astype(np.float32)
+    res = rng.integers(3, 1025, size=3)
+    res = np.where((res & (res - 1)) == 0, res + 1, res).astype(np.uint32)   # no powers of two
+    return lo, hi, res
+
+
+def test_fp32_map_matches_rational_model_at_cell_faces():
+    # the map is a fixed FP32 sequence (Section 3 leaves it open; the reading is
+    # floor((p - lo) * inv) with inv = res / (hi - lo), each step rounded once):
+    # every box corner the oracle reports must equal that sequence evaluated in
+    # exact rationals with an explicit round-to-nearest-even, on grids whose inv
+    # is not a power of two and on points at and beside the cell faces.
+    rng = np.random.default_rng(11)
+    differs = 0
+    checked = 0
+    for _ in range(12):
+        lo, hi, res = _non_dyadic_grid(rng)
+        axes = [_face_points(rng, lo[a], hi[a], int(res[a])) for a in range(3)]
+        n = max(len(x) for x in axes)
+        picks = [rng.choice(axes[a], size=(n, 3)) for a in range(3)]
+        # vertex j of triangle t on axis a is picks[a][t, j]
+        verts = np.stack([picks[a].reshape(-1) for a in range(3)]).astype(np.float32)
+        tris = np.arange(3 * n, dtype=np.uint32).reshape(n, 3)
+        box_lo, box_m, _ = oracle.count_cells(verts, tris, lo, hi, res)
+        for a in range(3):
+            memo = {}
+
+            def model(p, a=a):
+                key = float(p)
+                if key not in memo:
+                    memo[key] = (fp32_model.cell_fp32(p, lo[a], hi[a], int(res[a])),
+                                 fp32_model.cell_exact(p, lo[a], hi[a], int(res[a])))
+                return memo[key]
+            for t in range(n):
+                pmin, pmax = picks[a][t].min(), picks[a][t].max()
+                want_lo, ex_lo = model(pmin)
+                want_hi, ex_hi = model(pmax)
+                assert int(box_lo[t, a]) == want_lo, (a, float(pmin), lo[a], hi[a], res[a])
+                assert int(box_lo[t, a]) + int(box_m[t, a]) - 1 == want_hi, (a, float(pmax), lo[a], hi[a], res[a])
+                checked += 2
+            differs += sum(1 for f, e in memo.values() if f != e)
+    # the inputs do reach the cases where rounding decides the cell
+    assert checked > 9000 and differs >= 100, (checked, differs)
+
+
+def test_fp32_map_face_case_rounds_up():
+    # (p - lo) * inv is just below 4 in exact arithmetic but rounds to 4.0 in
+    # FP32: the contract's sequence puts the point in cell 4, exact arithmetic in 3
+    lo, hi, res = np.zeros(3, np.float32), np.full(3, np.float32(17.219383)), np.full(3, 112, np.uint32)
+    p = np.float32(0.61497796)
+    assert fp32_model.cell_fp32(p, lo[0], hi[0], 112) == 4
+    assert fp32_model.cell_exact(p, lo[0], hi[0], 112) == 3
+    verts, tris = _soup([[[p, p, p], [p, p, p], [p, p, p]]])
+    box_lo, box_m, count = oracle.count_cells(verts, tris, lo, hi, res)
+    assert box_lo[0].tolist() == [4, 4, 4] and count.tolist() == [1]
+    assert np.float32(oracle.inv_cell(lo, hi, res)[0]) == np.float32(fp32_model.inv_cell(lo[0], hi[0], 112))
+
+
+def test_rational_rounding_model_matches_ieee_binary32():
+    # the model itself, against the host's binary32 arithmetic (normal,
+    # subnormal and overflowing results)
+    rng = np.random.default_rng(5)
+    a = (rng.standard_normal(3000) * 10.0 ** rng.integers(-30, 30, 3000)).astype(np.float32)
+    b = (rng.standard_normal(3000) * 10.0 ** rng.integers(-30, 30, 3000)).astype(np.float32)
+    with np.errstate(all="ignore"):
+        for hw, ex in ((a * b, lambda x, y: x * y), (a / b, lambda x, y: x / y), (a - b, lambda x, y: x - y)):
+            for x, y, h in zip(a, b, hw):
+                m = fp32_model.rn32(ex(fp32_model.exact(x), fp32_model.exact(y)))
+                if np.isinf(h):
+                    assert m == (math.inf if h > 0 else -math.inf)
+                else:
+                    assert m == fp32_model.exact(h)
 
 
 def test_invalid_grid_and_bad_index():
