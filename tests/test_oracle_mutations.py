@@ -3,8 +3,7 @@
 Each case plants one mistake (a wrong index, a dropped term, a flipped sign, a
 swapped operand) into a private copy of the oracle's source, compiles it on the
 CPU, and checks that the brute-force, GlobalCoords and FP32 cell-face pins
-reject it.  The
-oracle itself is never modified.
+reject it.  The oracle itself is never modified.
 """
 import ctypes as C
 import multiprocessing as mp
