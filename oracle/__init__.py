@@ -60,6 +60,14 @@ def lib():
         L.oracle_ranges.argtypes = [C.c_uint64, P, C.c_uint64, P]
         L.oracle_build.argtypes = [P, C.c_uint32, P, C.c_uint32, P, P, P, P, P, P, C.c_uint64, P]
         L.oracle_build.restype = C.c_int
+        L.oracle_grid_coords.argtypes = [P, C.c_uint32, P, P, P, P, P]
+        L.oracle_grid_coords.restype = C.c_int
+        L.oracle_touches.argtypes = [P, C.c_uint32, C.c_uint32, C.c_uint32]
+        L.oracle_touches.restype = C.c_int
+        L.oracle_make_pairs_culled.argtypes = [P, C.c_uint32, P, C.c_uint32, P, P, P, P, P, P, P, P, P]
+        L.oracle_make_pairs_culled.restype = C.c_uint64
+        L.oracle_build_culled.argtypes = [P, C.c_uint32, P, C.c_uint32, P, P, P, P, P, P, C.c_uint64, P, P]
+        L.oracle_build_culled.restype = C.c_int
         _lib = L
     return _lib
 
@@ -204,3 +212,68 @@ def build_scene(scene, stages: bool = False):
     if stages:
         return build_stages(scene.verts, scene.tris, scene.lo, scene.hi, scene.res)
     return build(scene.verts, scene.tris, scene.lo, scene.hi, scene.res)
+
+
+# --- removal of false intersections (Test Results, Hairball; Conclusions) ----------------
+
+def grid_coords(verts, tri, lo, hi, res):
+    """Grid coordinates u[j][axis] of one triangle's vertices (the FP32 values the
+    cell map floors) and whether the overlap test applies to it."""
+    verts = np.ascontiguousarray(verts, np.float32)
+    tri = np.ascontiguousarray(tri, np.uint32)
+    lo, hi, res = _grid_args(lo, hi, res)
+    inv = inv_cell(lo, hi, res)
+    u = np.zeros((3, 3), np.float32)
+    inside = lib().oracle_grid_coords(_p(verts), verts.shape[1], _p(tri), _p(lo), _p(inv), _p(res), _p(u))
+    return u, bool(inside)
+
+
+def touches(u, cell_xyz) -> bool:
+    """The FP32 overlap test of a triangle (grid coordinates u [3, 3]) with a cell."""
+    u = np.ascontiguousarray(u, np.float32)
+    x, y, z = (int(v) for v in cell_xyz)
+    return bool(lib().oracle_touches(_p(u), x, y, z))
+
+
+def make_pairs_culled(verts, tris, lo, hi, res, box_lo, box_m, count):
+    """Object-order pairs with false intersections removed: (cells, objs, kept per triangle)."""
+    verts = np.ascontiguousarray(verts, np.float32)
+    tris = np.ascontiguousarray(tris, np.uint32)
+    lo, hi, res = _grid_args(lo, hi, res)
+    box_lo = np.ascontiguousarray(box_lo, np.uint32)
+    box_m = np.ascontiguousarray(box_m, np.uint32)
+    count = np.ascontiguousarray(count, np.uint32)
+    nbox = int(count.astype(np.uint64).sum())
+    cells = np.zeros(max(nbox, 1), np.uint32)
+    objs = np.zeros(max(nbox, 1), np.uint32)
+    kept = np.zeros(tris.shape[0], np.uint32)
+    n = lib().oracle_make_pairs_culled(_p(verts), verts.shape[1], _p(tris), tris.shape[0], _p(lo), _p(hi), _p(res),
+                                       _p(box_lo), _p(box_m), _p(count), _p(cells), _p(objs), _p(kept))
+    return cells[:n], objs[:n], kept
+
+
+def build_culled(verts, tris, lo, hi, res):
+    """Whole build with false intersections removed: (cells, objs, ranges, box pair count)."""
+    verts = np.ascontiguousarray(verts, np.float32)
+    tris = np.ascontiguousarray(tris, np.uint32)
+    lo, hi, res = _grid_args(lo, hi, res)
+    no = np.zeros(1, np.uint64)
+    nbox = np.zeros(1, np.uint64)
+    st = lib().oracle_build_culled(_p(verts), verts.shape[1], _p(tris), tris.shape[0], _p(lo), _p(hi), _p(res),
+                                   None, None, None, 0, _p(no), _p(nbox))
+    if st != 0:
+        raise OracleError(st)
+    n = int(no[0])
+    ncells = int(np.prod(res.astype(np.int64)))
+    cells = np.zeros(max(n, 1), np.uint32)
+    objs = np.zeros(max(n, 1), np.uint32)
+    rg = np.zeros(2 * ncells, np.uint32)
+    st = lib().oracle_build_culled(_p(verts), verts.shape[1], _p(tris), tris.shape[0], _p(lo), _p(hi), _p(res),
+                                   _p(cells), _p(objs), _p(rg), n, _p(no), _p(nbox))
+    if st != 0:
+        raise OracleError(st)
+    return cells[:n], objs[:n], rg, int(nbox[0])
+
+
+def build_scene_culled(scene):
+    return build_culled(scene.verts, scene.tris, scene.lo, scene.hi, scene.res)

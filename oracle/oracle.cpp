@@ -47,6 +47,9 @@ inline uint32_t cell_coord(float p, float lo, float inv, uint32_t res) {
   return static_cast<uint32_t>(f);
 }
 
+// Linear cell id, x varying fastest (the order GlobalCoords enumerates a box).
+inline uint32_t linear_id(const uint32_t g[3], const uint32_t res[3]) { return g[0] + res[0] * (g[1] + res[1] * g[2]); }
+
 bool valid_grid(const float lo[3], const float hi[3], const uint32_t res[3]) {
   for (int a = 0; a < 3; ++a) {
     if (!std::isfinite(lo[a]) || !std::isfinite(hi[a]) || !(lo[a] < hi[a])) return false;
@@ -131,7 +134,7 @@ void oracle_make_pairs(uint32_t ntris, const uint32_t* box_lo, const uint32_t* b
     for (uint32_t rid = 0; rid < count[t]; ++rid) {
       uint32_t g[3];
       oracle_global_coords(box_lo + 3 * static_cast<size_t>(t), box_m + 3 * static_cast<size_t>(t), rid, g);
-      cells[i] = g[0] + res[0] * (g[1] + res[1] * g[2]);
+      cells[i] = linear_id(g, res);
       objs[i] = t;
       ++i;
     }
@@ -184,6 +187,162 @@ int oracle_build(const float* verts_soa, uint32_t nverts, const uint32_t* tris, 
   if (ranges == nullptr) return kOk;
   if (no > cap_pairs) return kCapacity;
   oracle_make_pairs(ntris, box_lo.data(), box_m.data(), count.data(), res, cells, objs);
+  oracle_sort_pairs(no, cells, objs);
+  uint64_t ncells = static_cast<uint64_t>(res[0]) * res[1] * res[2];
+  oracle_ranges(no, cells, ncells, ranges);
+  return kOk;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Removal of false intersections (the fix the Test Results section suggests for
+// scenes of long thin diagonal triangles such as Hairball, and the Conclusions
+// list as future work): a pair <t, c> from t's cell box is kept only when the
+// triangle touches the cell.  Readings (the paper gives no test):
+//  * the test runs in grid coordinates: each vertex coordinate is the FP32
+//    value the cell map floors, u = (p - lo) * inv, so cell (x, y, z) is the
+//    closed unit box [x, x+1] x [y, y+1] x [z, z+1];
+//  * a separating-axis test over the triangle's normal and the nine cross
+//    products of its edges with the grid axes (the three face axes are
+//    implied by the cell box), every operation one FP32 operation in the
+//    order written here, with the cell widened by kOverlapMargin on every
+//    side so rounding can keep a false pair but never drop a true one;
+//  * a triangle keeps its whole box when a vertex lies outside [0, res] on
+//    some axis (or is NaN), and when its box holds at most two cells (it then
+//    touches every one of them).
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr float kOverlapMargin = 1.0f / 64.0f;  // cells
+
+inline float dot3(const float a[3], const float b[3]) {
+  float s = a[0] * b[0];
+  s = s + a[1] * b[1];
+  s = s + a[2] * b[2];
+  return s;
+}
+
+// True when axis a separates the triangle (grid coordinates u[j][axis]) from
+// the widened cell whose lower corner is b.
+bool axis_separates(const float a[3], const float u[3][3], const float b[3]) {
+  const float p0 = dot3(a, u[0]), p1 = dot3(a, u[1]), p2 = dot3(a, u[2]);
+  const float tmin = std::fmin(std::fmin(p0, p1), p2);
+  const float tmax = std::fmax(std::fmax(p0, p1), p2);
+  float lo_off = std::fmin(a[0], 0.0f) + std::fmin(a[1], 0.0f);
+  lo_off = lo_off + std::fmin(a[2], 0.0f);
+  float hi_off = std::fmax(a[0], 0.0f) + std::fmax(a[1], 0.0f);
+  hi_off = hi_off + std::fmax(a[2], 0.0f);
+  float l1 = std::fabs(a[0]) + std::fabs(a[1]);
+  l1 = l1 + std::fabs(a[2]);
+  const float mg = kOverlapMargin * l1;
+  // the cell projects onto [c + lo_off, c + hi_off] (widened by mg)
+  const float c = dot3(a, b);
+  const float above = (tmax + mg) - lo_off;
+  const float below = (tmin - mg) - hi_off;
+  return c > above || c < below;
+}
+
+// True when the triangle with grid coordinates u touches the widened cell b.
+bool triangle_touches_cell(const float u[3][3], const float b[3]) {
+  float e[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int a = 0; a < 3; ++a) e[i][a] = u[(i + 1) % 3][a] - u[i][a];
+  const float n[3] = {e[0][1] * e[1][2] - e[0][2] * e[1][1], e[0][2] * e[1][0] - e[0][0] * e[1][2],
+                      e[0][0] * e[1][1] - e[0][1] * e[1][0]};
+  if (axis_separates(n, u, b)) return false;
+  for (int i = 0; i < 3; ++i) {
+    const float ax[3] = {0.0f, e[i][2], -e[i][1]};   // e x (1, 0, 0)
+    const float ay[3] = {-e[i][2], 0.0f, e[i][0]};   // e x (0, 1, 0)
+    const float az[3] = {e[i][1], -e[i][0], 0.0f};   // e x (0, 0, 1)
+    if (axis_separates(ax, u, b) || axis_separates(ay, u, b) || axis_separates(az, u, b)) return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Grid coordinates of triangle t's vertices (u[j][axis]); returns 1 when the
+// overlap test applies to t (every coordinate finite and inside [0, res]).
+int oracle_grid_coords(const float* verts_soa, uint32_t nverts, const uint32_t* tri, const float lo[3],
+                       const float inv[3], const uint32_t res[3], float u[3][3]) {
+  int inside = 1;
+  for (int j = 0; j < 3; ++j)
+    for (int a = 0; a < 3; ++a) {
+      const float p = verts_soa[static_cast<size_t>(a) * nverts + tri[j]];
+      const float sft = p - lo[a];
+      u[j][a] = sft * inv[a];
+      if (!(u[j][a] >= 0.0f && u[j][a] <= static_cast<float>(res[a]))) inside = 0;
+    }
+  return inside;
+}
+
+// 1 when the triangle with grid coordinates u (float [3][3]) touches cell (x, y, z).
+int oracle_touches(const float* u, uint32_t x, uint32_t y, uint32_t z) {
+  float uu[3][3];
+  for (int j = 0; j < 3; ++j)
+    for (int a = 0; a < 3; ++a) uu[j][a] = u[3 * j + a];
+  const float b[3] = {static_cast<float>(x), static_cast<float>(y), static_cast<float>(z)};
+  return triangle_touches_cell(uu, b) ? 1 : 0;
+}
+
+// The object-order pair lists with false intersections removed: the pairs of
+// oracle_make_pairs, in the same order, less those whose triangle misses the
+// cell.  cells/objs hold at least NO (box) entries; returns the kept count and
+// writes each triangle's kept count to kept (if not null).
+uint64_t oracle_make_pairs_culled(const float* verts_soa, uint32_t nverts, const uint32_t* tris, uint32_t ntris,
+                                  const float lo[3], const float hi[3], const uint32_t res[3],
+                                  const uint32_t* box_lo, const uint32_t* box_m, const uint32_t* count,
+                                  uint32_t* cells, uint32_t* objs, uint32_t* kept) {
+  float inv[3];
+  oracle_inv_cell(lo, hi, res, inv);
+  uint64_t i = 0;
+  for (uint32_t t = 0; t < ntris; ++t) {
+    float u[3][3];
+    const int inside = oracle_grid_coords(verts_soa, nverts, tris + 3 * static_cast<size_t>(t), lo, inv, res, u);
+    const bool test = inside && count[t] > 2;
+    uint32_t k = 0;
+    for (uint32_t rid = 0; rid < count[t]; ++rid) {
+      uint32_t g[3];
+      oracle_global_coords(box_lo + 3 * static_cast<size_t>(t), box_m + 3 * static_cast<size_t>(t), rid, g);
+      if (test) {
+        const float b[3] = {static_cast<float>(g[0]), static_cast<float>(g[1]), static_cast<float>(g[2])};
+        if (!triangle_touches_cell(u, b)) continue;
+      }
+      cells[i] = linear_id(g, res);
+      objs[i] = t;
+      ++i;
+      ++k;
+    }
+    if (kept) kept[t] = k;
+  }
+  return i;
+}
+
+// Whole build with false intersections removed: as oracle_build, over the
+// kept pairs.  *npairs = the kept count; with ranges == nullptr only the
+// count is reported.  *box_npairs (if not null) = the box pair count.
+int oracle_build_culled(const float* verts_soa, uint32_t nverts, const uint32_t* tris, uint32_t ntris,
+                        const float lo[3], const float hi[3], const uint32_t res[3], uint32_t* cells, uint32_t* objs,
+                        uint32_t* ranges, uint64_t cap_pairs, uint64_t* npairs, uint64_t* box_npairs) {
+  std::vector<uint32_t> box_lo(3 * static_cast<size_t>(ntris)), box_m(3 * static_cast<size_t>(ntris)), count(ntris);
+  int st = oracle_count_cells(verts_soa, nverts, tris, ntris, lo, hi, res, box_lo.data(), box_m.data(), count.data());
+  if (st != kOk) return st;
+  std::vector<uint64_t> start(ntris);
+  const uint64_t nbox = oracle_exclusive_sum(count.data(), ntris, start.data());
+  if (box_npairs) *box_npairs = nbox;
+  if (nbox > 0xFFFFFFFFull) return kOverflow;
+  std::vector<uint32_t> c(nbox), o(nbox);
+  const uint64_t no = oracle_make_pairs_culled(verts_soa, nverts, tris, ntris, lo, hi, res, box_lo.data(),
+                                               box_m.data(), count.data(), c.data(), o.data(), nullptr);
+  *npairs = no;
+  if (ranges == nullptr) return kOk;
+  if (no > cap_pairs) return kCapacity;
+  std::copy(c.begin(), c.begin() + no, cells);
+  std::copy(o.begin(), o.begin() + no, objs);
   oracle_sort_pairs(no, cells, objs);
   uint64_t ncells = static_cast<uint64_t>(res[0]) * res[1] * res[2];
   oracle_ranges(no, cells, ncells, ranges);

@@ -55,3 +55,38 @@ def dyadic_scene(rng: np.random.Generator, ntris: int, lo: float, hi: float, spr
     verts = np.ascontiguousarray(v.reshape(ntris * 3, 3).T.astype(np.float32))
     tris = np.arange(3 * ntris, dtype=np.uint32).reshape(ntris, 3)
     return verts, tris
+
+
+def _clip(poly, axis, bound, keep_above):
+    """Sutherland-Hodgman: the part of polygon poly (list of rational 3-points) on
+    one closed side of the plane coordinate[axis] = bound."""
+    def inside(p):
+        return p[axis] >= bound if keep_above else p[axis] <= bound
+    out = []
+    n = len(poly)
+    for i in range(n):
+        p, q = poly[i], poly[(i + 1) % n]
+        ip, iq = inside(p), inside(q)
+        if ip:
+            out.append(p)
+        if ip != iq and p[axis] != q[axis]:
+            t = (bound - p[axis]) / (q[axis] - p[axis])
+            r = tuple(p[a] + t * (q[a] - p[a]) for a in range(3))
+            if inside(r):
+                out.append(r)
+    return out
+
+
+def triangle_touches_box(tri, lower, upper) -> bool:
+    """Exact test: does the closed triangle (3 rational 3-points) meet the closed
+    box [lower, upper]?  The triangle is clipped by the box's six half-spaces;
+    they meet iff something is left."""
+    poly = [tuple(Fraction(c) for c in p) for p in tri]
+    for a in range(3):
+        poly = _clip(poly, a, Fraction(lower[a]), True)
+        if not poly:
+            return False
+        poly = _clip(poly, a, Fraction(upper[a]), False)
+        if not poly:
+            return False
+    return True

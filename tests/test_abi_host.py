@@ -171,3 +171,30 @@ def test_tune_rejects_bad_values(G):
         G.tune_set("per_object_pairs", 2)
     assert G.tune_get("max_digit_bits") == 9 and G.tune_get("fused_expand") in (0, 1)
     assert G.tune_get("per_object_pairs") == 0
+
+
+def test_workspace_size_follows_the_digit_width(G):
+    # a 22-bit key (160^3 cells): 11-bit digits need more look-back words than
+    # 8-bit ones, and the binding must not serve a size computed under another width
+    from paper_2403_10647_amd import tune
+    res = [160, 160, 160]
+    old = G.tune_get("max_digit_bits")
+    try:
+        G.tune_set("max_digit_bits", 8)
+        a = G.workspace_size(1_000_000, 33_000_000, res)
+        G.tune_set("max_digit_bits", 11)
+        b = G.workspace_size(1_000_000, 33_000_000, res)
+    finally:
+        G.tune_set("max_digit_bits", old)
+    assert b > a
+
+    class _G:   # the tuner's sizing over its candidates, on the host only
+        tune_get = staticmethod(G.tune_get)
+        tune_set = staticmethod(G.tune_set)
+        workspace_size = staticmethod(G.workspace_size)
+
+    class _g:
+        ntris = 1_000_000
+    _g.res = res
+    assert tune.max_workspace(_G, _g, 33_000_000) == b
+    assert G.tune_get("max_digit_bits") == old

@@ -56,7 +56,7 @@ def _check_alone(G, reqs, refs):
 
 def test_refs_match_oracle(G, workload):
     pool_scenes, big_scene, pool, big, refs = workload
-    for i in (0, 7, 15):
+    for i in range(len(pool)):
         c, o, r = refs[i].numpy()
         oc, oo, orr = oracle.build_scene(pool_scenes[i])
         assert np.array_equal(c, oc) and np.array_equal(o, oo) and np.array_equal(r, orr)
@@ -76,6 +76,7 @@ def test_served_in_the_mix_equals_alone(G, workload):
     assert st.completed == len(reqs) and st.rejected == 0 and st.failed == 0
     assert st.mismatches == 0 and st.verified == len(reqs)
     assert st.batches < len(reqs)          # requests were batched together
+    assert st.peak_slots > 1               # and batches were on the device at the same time
     _check_alone(G, reqs, refs)
 
 

@@ -48,3 +48,17 @@ def test_tune_batched(G, tmp_path):
     best, table = tune.tune_batched(inputs, reps=2, space=SPACE, cache_path=str(tmp_path / "t.json"), G=G)
     assert all(r["identical"] for r in table)
     assert all(G.tune_get(k) == v for k, v in tune.DEFAULTS.items())   # the tuner restores the knobs
+
+
+def test_tune_plain_wide_key(G, tmp_path):
+    # 160^3 cells = a 22-bit key, where 11-bit digits need a larger workspace
+    # than the default setting: the tuner must size for every candidate
+    base = scenes.make_scene("mixed", seed=9, ntris=30_000)
+    s = scenes.Scene("mixed22", base.verts, base.tris, base.lo, base.hi, np.array([160, 160, 160], np.uint32))
+    g = G.GridInput.from_scene(s)
+    best, table = tune.tune_plain(g, reps=1, space={"max_digit_bits": (8, 11), "sort_shape": (3,),
+                                                    "fused_expand": (0,)}, G=G)
+    assert len(table) == 2 and all(r["identical"] for r in table)
+    c, o, r = G.build(g).numpy()
+    oc, oo, orr = oracle.build_scene(s)
+    assert np.array_equal(c, oc) and np.array_equal(o, oo) and np.array_equal(r, orr)

@@ -23,7 +23,8 @@ MUTATIONS = {
     "globalcoords_z_divisor": ("uint32_t z = rid / (m[0] * m[1]);", "uint32_t z = rid / (m[0] * m[2]);"),
     "globalcoords_x_term": ("rid - m[0] * (y + m[1] * z)", "rid - m[0] * (y + m[0] * z)"),
     "globalcoords_y_offset": ("out[1] = box_lo[1] + y;", "out[1] = box_lo[0] + y;"),
-    "linearise_transposed": ("g[0] + res[0] * (g[1] + res[1] * g[2])", "g[0] + res[1] * (g[1] + res[0] * g[2])"),
+    "linearise_transposed": ("return g[0] + res[0] * (g[1] + res[1] * g[2]);",
+                             "return g[0] + res[1] * (g[1] + res[0] * g[2]);"),
     "map_round_not_floor": ("float f = std::floor(u);", "float f = std::round(u);"),
     "map_no_low_clamp": ("f = std::fmax(f, 0.0f);", ""),
     "map_wrong_sign": ("float s = p - lo;", "float s = lo - p;"),
@@ -41,6 +42,13 @@ MUTATIONS = {
     "map_double_intermediate": ("float s = p - lo;\n  float u = s * inv;\n  float f = std::floor(u);",
                                 "double s = static_cast<double>(p) - lo;\n  double u = s * inv;\n"
                                 "  float f = static_cast<float>(std::floor(u));"),
+    # removal of false intersections
+    "cull_edge_axis_component": ("const float ax[3] = {0.0f, e[i][2], -e[i][1]};",
+                                 "const float ax[3] = {0.0f, e[i][1], -e[i][2]};"),
+    "cull_normal_component": ("e[0][2] * e[1][0] - e[0][0] * e[1][2]", "e[0][2] * e[1][0] - e[0][1] * e[1][2]"),
+    "cull_no_normal_axis": ("  if (axis_separates(n, u, b)) return false;\n", ""),
+    "cull_margin_shrinks": ("const float above = (tmax + mg) - lo_off;", "const float above = (tmax - mg) - lo_off;"),
+    "cull_box_offset_swapped": ("const float below = (tmin - mg) - hi_off;", "const float below = (tmin - mg) - lo_off;"),
 }
 
 
@@ -61,6 +69,8 @@ def _compile(tmp_path, name, src):
     L.oracle_global_coords.argtypes = [P, P, C.c_uint32, P]
     L.oracle_count_cells.argtypes = [P, C.c_uint32, P, C.c_uint32, P, P, P, P, P, P]
     L.oracle_count_cells.restype = C.c_int
+    L.oracle_make_pairs_culled.argtypes = [P, C.c_uint32, P, C.c_uint32, P, P, P, P, P, P, P, P, P]
+    L.oracle_make_pairs_culled.restype = C.c_uint64
     return L
 
 
@@ -113,9 +123,75 @@ def _faces_pass(L) -> bool:
     return True
 
 
+def _cull_cases():
+    """Scenes of slivers and random triangles on non-dyadic grids, with every box
+    cell's exact touch (rational clip of the FP32 grid coordinates by the cell)
+    and near-touch (the cell widened by twice the margin)."""
+    from fractions import Fraction
+    from brute import triangle_touches_box
+    from paper_2403_10647_amd import scenes
+    cases = []
+    for seed in (3, 4):
+        rng = np.random.default_rng(seed)
+        lo = rng.uniform(-5, 5, size=3).astype(np.float32)
+        hi = (lo + rng.uniform(4.1, 8.9, size=3)).astype(np.float32)
+        res = rng.integers(6, 12, size=3).astype(np.uint32)
+        a = rng.uniform(lo + 0.1, hi - 0.1, size=(20, 3))
+        b = rng.uniform(lo + 0.1, hi - 0.1, size=(20, 3))
+        w = np.clip(b + rng.normal(size=(20, 3)) * 0.3, lo + 0.05, hi - 0.05)
+        verts, tris = scenes.soup_from_vertices(np.stack([a, b, w], axis=1))
+        box_lo, box_m, count = oracle.count_cells(verts, tris, lo, hi, res)
+        m2 = 2 * Fraction(1, 64)
+        want = []
+        for t in range(tris.shape[0]):
+            u = []
+            for j in range(3):
+                u.append(tuple(fp32_model.rn32(fp32_model.rn32(fp32_model.exact(verts[ax][tris[t, j]])
+                                                               - fp32_model.exact(lo[ax]))
+                                               * fp32_model.inv_cell(lo[ax], hi[ax], int(res[ax]))) for ax in range(3)))
+            for z in range(int(box_m[t, 2])):
+                for y in range(int(box_m[t, 1])):
+                    for x in range(int(box_m[t, 0])):
+                        c = (int(box_lo[t, 0]) + x, int(box_lo[t, 1]) + y, int(box_lo[t, 2]) + z)
+                        cid = c[0] + int(res[0]) * (c[1] + int(res[1]) * c[2])
+                        touch = triangle_touches_box(u, c, tuple(v + 1 for v in c))
+                        near = triangle_touches_box(u, tuple(v - m2 for v in c), tuple(v + 1 + m2 for v in c))
+                        want.append((t, cid, touch, near, int(count[t]) <= 2))
+        cases.append((verts, tris, lo, hi, res, box_lo, box_m, count, want))
+    return cases
+
+
+_CULL_CASES = None
+
+
+def _cull_pass(L) -> bool:
+    global _CULL_CASES
+    if _CULL_CASES is None:
+        _CULL_CASES = _cull_cases()
+    for verts, tris, lo, hi, res, box_lo, box_m, count, want in _CULL_CASES:
+        nbox = int(count.sum())
+        cells = np.zeros(nbox, np.uint32)
+        objs = np.zeros(nbox, np.uint32)
+        kept = np.zeros(tris.shape[0], np.uint32)
+        n = L.oracle_make_pairs_culled(_p(verts), verts.shape[1], _p(tris), tris.shape[0], _p(lo), _p(hi), _p(res),
+                                       _p(box_lo), _p(box_m), _p(count), _p(cells), _p(objs), _p(kept))
+        got = set(zip(objs[:n].tolist(), cells[:n].tolist()))
+        dropped = 0
+        for t, cid, touch, near, whole in want:
+            k = (t, cid) in got
+            if (whole or touch) and not k:
+                return False
+            if k and not near:
+                return False
+            dropped += not k
+        if dropped == 0:
+            return False
+    return True
+
+
 def _pins_pass(L) -> bool:
-    """Run the brute-force, GlobalCoords and FP32 cell-face pins against library L."""
-    if not _faces_pass(L):
+    """Run the brute-force, GlobalCoords, FP32 cell-face and culling pins against library L."""
+    if not _faces_pass(L) or not _cull_pass(L):
         return False
     lo5 = np.array([5, 7, 11], np.uint32)
     for m in [(2, 3, 4), (3, 1, 2), (4, 4, 1)]:

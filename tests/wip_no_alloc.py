@@ -1,0 +1,75 @@
+"""grid_build_static (the build whose scratch is the library's static device
+array) against grid_build (the same build in a caller's workspace), bit for bit,
+on two calls in a row, the second on a smaller scene, so the second call runs
+over the scratch the first one left behind."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_10647_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_10647_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+def _outputs(G, g, cap):
+    return G.GridResult(torch.full((max(cap, 1),), -1, dtype=torch.int32, device="cuda"),
+                        torch.full((max(cap, 1),), -1, dtype=torch.int32, device="cuda"),
+                        torch.full((2 * g.ncells,), -1, dtype=torch.int32, device="cuda"), 0)
+
+
+def _same(a, b):
+    n = a.npairs
+    return (a.npairs == b.npairs and torch.equal(a.cells[:n], b.cells[:n]) and torch.equal(a.objs[:n], b.objs[:n])
+            and torch.equal(a.ranges, b.ranges))
+
+
+def test_static_build_equals_workspace_build_twice(G):
+    big = scenes.make_scene("mixed", seed=3, ntris=150_000)
+    small = scenes.make_scene("small", seed=0)
+    for s in (big, small):   # the second call is the smaller one
+        print("static build", s.name, s.ntris, list(map(int, s.res)), flush=True)
+        g = G.GridInput.from_scene(s)
+        n, _ = G.count(g)
+        assert G.workspace_size(g.ntris, n, g.res) <= G.STATIC_SCRATCH_BYTES
+        ref = G.build(g, cap_pairs=n, out=_outputs(G, g, n))
+        got = G.build_static(g, _outputs(G, g, n))
+        torch.cuda.synchronize()
+        assert got.npairs == n and _same(got, ref)
+    c, o, r = got.numpy()
+    oc, oo, orr = oracle.build_scene(small)
+    assert np.array_equal(c, oc) and np.array_equal(o, oo) and np.array_equal(r, orr)
+
+
+def test_static_build_rejects_more_than_its_scratch(G):
+    s = scenes.make_scene("small", seed=0)
+    g = G.GridInput.from_scene(s)
+    cap = 20_000_000   # needs far more workspace than the static scratch holds
+    assert G.workspace_size(g.ntris, cap, g.res) > G.STATIC_SCRATCH_BYTES
+    dummy = torch.zeros(16, dtype=torch.int32, device="cuda")
+    o = G.grid_out(dummy.data_ptr(), dummy.data_ptr(), dummy.data_ptr(), cap, 0)
+    st = G.lib().grid_build_static(*G._input_args(g), C.byref(o), G._stream())
+    assert st == G.GRID_E_NOMEM
+    assert not dummy.any()       # rejected before any device work
+
+
+def test_static_build_capacity_error_reports_npairs(G):
+    s = scenes.make_scene("small", seed=1)
+    g = G.GridInput.from_scene(s)
+    n, _ = G.count(g)
+    out = _outputs(G, g, n - 1)
+    with pytest.raises(G.GridError) as e:
+        G.build_static(g, out)
+    assert e.value.status == G.GRID_E_CAPACITY and out.npairs == n
