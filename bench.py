@@ -292,7 +292,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip serving")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the per-object pair generation comparison")
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-budget-gb", type=int, default=64)
     ap.add_argument("--serve-slots", type=int, default=3)

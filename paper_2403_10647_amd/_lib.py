@@ -224,7 +224,8 @@ _ws_sizes: dict = {}
 
 
 def workspace_size(ntris: int, cap_pairs: int, res) -> int:
-    key = (int(ntris), int(cap_pairs), tuple(int(r) for r in res))
+    # the radix digit width sets the look-back words the workspace holds
+    key = (int(ntris), int(cap_pairs), tuple(int(r) for r in res), tune_get("max_digit_bits"))
     n = _ws_sizes.get(key)
     if n is None:
         n = _ws_sizes[key] = int(lib().grid_workspace_size(ntris, cap_pairs, _u3(res)))

@@ -132,6 +132,7 @@ class ServeStats:
     budget_bytes: int
     verified: int
     mismatches: int
+    peak_slots: int = 0            # most batches on the device at one time
 
     def as_dict(self):
         return dataclasses.asdict(self)
@@ -261,6 +262,7 @@ class Server:
         queue: List[Request] = []
         used = 0
         peak = 0
+        peak_slots = 0
         nxt = 0
         finished = 0
         batches = 0
@@ -315,6 +317,7 @@ class Server:
                 del queue[:launched]
                 used += s.bytes
                 peak = max(peak, used)
+                peak_slots = max(peak_slots, sum(1 for x in self.slots if x.batch))
                 batches += 1
                 batched += launched
             if not queue and all(not s.batch for s in self.slots) and nxt < n:
@@ -335,7 +338,7 @@ class Server:
             duration_s=t_end, builds_per_s=len(ok) / span, pairs_per_s=sum(r.npairs for r in ok) / span,
             p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)), max_ms=float(lat.max()),
             batches=batches, mean_batch=batched / max(batches, 1), peak_bytes=peak, budget_bytes=self.budget,
-            verified=len(ok) if self.refs is not None else 0, mismatches=mism)
+            verified=len(ok) if self.refs is not None else 0, mismatches=mism, peak_slots=peak_slots)
 
 
 def poisson_arrivals(rate: float, duration: float, seed: int) -> np.ndarray:

@@ -90,6 +90,23 @@ def _key_bits(ncells: int) -> int:
     return max(1, (ncells - 1).bit_length())
 
 
+def max_workspace(G, g, npairs: int, space=None) -> int:
+    """Workspace bytes a plain build of ``g`` needs under the widest-sized of the
+    candidate digit widths (a wider digit keeps more look-back words per tile)."""
+    sp = dict(SPACE)
+    if space:
+        sp.update(space)
+    old = G.tune_get("max_digit_bits")
+    try:
+        need = 0
+        for d in sp["max_digit_bits"]:
+            G.tune_set("max_digit_bits", int(d))
+            need = max(need, G.workspace_size(g.ntris, npairs, g.res))
+    finally:
+        G.tune_set("max_digit_bits", old)
+    return need
+
+
 def tune_plain(g, reps: int = 5, space=None, cache_path: Optional[str] = None, G=None) -> Tuple[Dict[str, int], list]:
     """Best setting for plain builds of ``g`` (a GridInput); returns (knobs, table)."""
     import torch
@@ -97,6 +114,7 @@ def tune_plain(g, reps: int = 5, space=None, cache_path: Optional[str] = None, G
         from . import _lib as G
     ws = G.Workspace()
     npairs, _ = G.count(g, ws)
+    ws.get(max_workspace(G, g, npairs, space))   # sized once for every candidate: PlainBuild keeps its pointer
     out = G.build(g, cap_pairs=npairs, ws=ws)
     run = G.PlainBuild(g, out, ws)
 
