@@ -157,6 +157,24 @@ int grid_build_batched_async(const grid_desc *grids, uint32_t ngrids, void *ws, 
  * pair count.  Synchronizes stream. */
 int grid_workspace_status(const void *ws, uint64_t *npairs_total, void *stream);
 
+/* ---- a build that allocates nothing ----------------------------------------- */
+
+/* For callers that cannot allocate device memory or take a workspace argument
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): grid_build with its workspace in a static device array of
+ * GRID_STATIC_SCRATCH_BYTES bytes that the library holds on every GPU it runs
+ * on until the process ends.  Arguments, outputs, synchronisation and status
+ * codes are grid_build's; the caller still owns inputs and outputs.  A build
+ * whose workspace (grid_workspace_size(ntris, out->cap_pairs, res)) exceeds
+ * the array returns GRID_E_NOMEM before any device work.  Every call on one
+ * GPU uses that GPU's single array, which keeps the last call's contents (the
+ * build clears what it needs zeroed): calls that overlap on one GPU (two host
+ * threads, or two streams without ordering) race and must be serialised by
+ * the caller. */
+#define GRID_STATIC_SCRATCH_BYTES (64ull << 20)
+int grid_build_static(const float *verts_soa, uint32_t nverts, const uint32_t *tris, uint32_t ntris,
+                      const float lo[3], const float hi[3], const uint32_t res[3], grid_out *out, void *stream);
+
 /* ---- building blocks, exposed for testing and reuse ------------------------ */
 
 /* Stable LSD radix sort of (keys, vals) by the low nbits bits of keys

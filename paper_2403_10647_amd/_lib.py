@@ -31,12 +31,14 @@ SCAN_INCLUSIVE_MAX = 1
 SCAN_SEGMENTED_EXCLUSIVE_SUM = 2
 
 EXPORTS = (
-    "grid_strerror", "grid_workspace_size", "grid_count", "grid_build", "grid_expand",
+    "grid_strerror", "grid_workspace_size", "grid_count", "grid_build", "grid_build_static", "grid_expand",
     "grid_workspace_size_batched", "grid_count_batched", "grid_build_batched",
     "grid_sort_workspace_size", "grid_sort_pairs", "grid_scan_workspace_size", "grid_scan_u32",
     "grid_trace_enable", "grid_trace_read", "grid_tune_set", "grid_tune_get", "grid_sort_plan",
     "grid_batch_staging_size", "grid_build_batched_async", "grid_workspace_status", "grid_trace_only",
 )
+
+STATIC_SCRATCH_BYTES = 64 << 20   # GRID_STATIC_SCRATCH_BYTES: the static workspace of grid_build_static
 
 
 class GridError(RuntimeError):
@@ -83,6 +85,7 @@ def lib():
         L.grid_workspace_size.restype = SZ
         L.grid_count.argtypes = [P, U32, P, U32, F3, F3, U3, P, SZ, P, C.POINTER(C.c_uint64), P]
         L.grid_build.argtypes = [P, U32, P, U32, F3, F3, U3, P, SZ, C.POINTER(grid_out), P]
+        L.grid_build_static.argtypes = [P, U32, P, U32, F3, F3, U3, C.POINTER(grid_out), P]
         L.grid_expand.argtypes = [P, U32, P, U32, F3, F3, U3, P, SZ, P, P, U64, C.POINTER(C.c_uint64), P]
         L.grid_workspace_size_batched.argtypes = [C.POINTER(grid_desc), U32]
         L.grid_workspace_size_batched.restype = SZ
@@ -110,7 +113,7 @@ def lib():
         L.grid_trace_only.argtypes = [C.c_char_p]
         L.grid_trace_only.restype = C.c_int
         L.grid_trace_read.argtypes = [C.POINTER(grid_trace_entry), C.c_int, C.POINTER(C.c_int)]
-        for name in ("grid_trace_enable", "grid_trace_read", "grid_count", "grid_build", "grid_expand", "grid_count_batched", "grid_build_batched",
+        for name in ("grid_trace_enable", "grid_trace_read", "grid_count", "grid_build", "grid_build_static", "grid_expand", "grid_count_batched", "grid_build_batched",
                      "grid_sort_pairs", "grid_scan_u32"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -263,6 +266,17 @@ def build(g: GridInput, cap_pairs: Optional[int] = None, ws: Optional[Workspace]
     st = L.grid_build(*_input_args(g), wp, wn, C.byref(o), _stream(stream))
     out.npairs = int(o.npairs)
     _check(st, "grid_build")
+    return out
+
+
+def build_static(g: GridInput, out: GridResult, stream=None) -> GridResult:
+    """The whole build in the library's static device scratch (grid_build_static):
+    no workspace argument and no allocation.  out's buffers set the capacity."""
+    cap = int(out.cells.numel())
+    o = grid_out(out.cells.data_ptr(), out.objs.data_ptr(), out.ranges.data_ptr(), cap, 0)
+    st = lib().grid_build_static(*_input_args(g), C.byref(o), _stream(stream))
+    out.npairs = int(o.npairs)
+    _check(st, "grid_build_static")
     return out
 
 

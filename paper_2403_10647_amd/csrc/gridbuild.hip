@@ -754,6 +754,53 @@ int grid_expand(const float* verts_soa, uint32_t nverts, const uint32_t* tris, u
 }  // extern "C"
 
 // ---------------------------------------------------------------------------------
+// The build whose workspace is a static device array (no allocation anywhere).
+// ---------------------------------------------------------------------------------
+// Each device that loads the library holds its own copy of this array.  In host
+// code its name is only a host-side stand-in: kernels and copies get the device
+// address that hipGetSymbolAddress returns for the current device.
+__device__ __align__(256) unsigned char scratch[GRID_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+// Device address of the current device's scratch array, looked up once per
+// device (with that device current) and kept for later calls.
+int static_scratch(void** out) {
+  static std::mutex mu;
+  static void* addr[64] = {};
+  int dev = -1;
+  GB_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return GRID_E_HIP;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    GB_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return GRID_E_HIP;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return GRID_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int grid_build_static(const float* verts_soa, uint32_t nverts, const uint32_t* tris, uint32_t ntris,
+                      const float lo[3], const float hi[3], const uint32_t res[3], grid_out* out, void* stream) {
+  if (!out || check_grid(lo, hi, res) != GRID_OK) return GRID_E_INVAL;
+  // the same sizing grid_build checks its workspace against, before any device work
+  const size_t need = grid_workspace_size(ntris, out->cap_pairs, res);
+  if (need == 0 || need > GRID_STATIC_SCRATCH_BYTES) return GRID_E_NOMEM;
+  void* ws = nullptr;
+  int st = static_scratch(&ws);
+  if (st) return st;
+  return grid_build(verts_soa, nverts, tris, ntris, lo, hi, res, ws, GRID_STATIC_SCRATCH_BYTES, out, stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------
 // Batched builds.
 // ---------------------------------------------------------------------------------
 namespace {

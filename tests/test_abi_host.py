@@ -198,3 +198,20 @@ def test_workspace_size_follows_the_digit_width(G):
     _g.res = res
     assert tune.max_workspace(_G, _g, 33_000_000) == b
     assert G.tune_get("max_digit_bits") == old
+
+
+def test_static_build_rejects_oversize_before_device_work(G):
+    """grid_build_static sizes its workspace on the host and refuses a build that
+    would not fit its static scratch (no device call is made)."""
+    m = re.search(r"#define GRID_STATIC_SCRATCH_BYTES \((\d+)ull << (\d+)\)", open(HEADER).read())
+    assert m and int(m.group(1)) << int(m.group(2)) == G.STATIC_SCRATCH_BYTES
+    o = G.grid_out(None, None, 1, 20_000_000, 0)
+    res = G._u3([32, 32, 32])
+    L = G.lib()
+    assert G.workspace_size(4096, 20_000_000, [32, 32, 32]) > G.STATIC_SCRATCH_BYTES
+    st = L.grid_build_static(None, 0, None, 4096, G._f3([0, 0, 0]), G._f3([1, 1, 1]), res, C.byref(o), None)
+    assert st == G.GRID_E_NOMEM
+    bad = G._u3([0, 32, 32])
+    assert L.grid_build_static(None, 0, None, 0, G._f3([0, 0, 0]), G._f3([1, 1, 1]), bad, C.byref(o), None) \
+        == G.GRID_E_INVAL
+    assert L.grid_build_static(None, 0, None, 0, G._f3([0, 0, 0]), G._f3([1, 1, 1]), res, None, None) == G.GRID_E_INVAL
