@@ -303,6 +303,7 @@ def main():
     ap.add_argument("--mode", default="bench", choices=["bench", "copy"])
     ap.add_argument("--max-digit-bits", type=int, default=None, help="override the radix digit width")
     ap.add_argument("--fused", type=int, default=None, choices=[0, 1], help="first radix pass regenerates keys")
+    ap.add_argument("--sort-shape", type=int, default=None, help="radix pass workgroup shape (grid_tune_set sort_shape)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -325,6 +326,8 @@ def main():
         G.tune_set("max_digit_bits", args.max_digit_bits)
     if args.fused is not None:
         G.tune_set("fused_expand", args.fused)
+    if args.sort_shape is not None:
+        G.tune_set("sort_shape", args.sort_shape)
     knobs = {k: G.tune_get(k) for k in ("max_digit_bits", "fused_expand", "sort_shape")}
     t0 = time.time()
     scene = scenes.make_scene(args.workload, seed=args.seed)
