@@ -240,6 +240,46 @@ def run_ablation(G, args, gin, out, ws, reps: int = 5) -> dict:
     return res
 
 
+def run_culled(G, args, gin, out, ws, reps: int = 5) -> dict:
+    """The build with false intersections removed (grid_build_culled) against the
+    plain build on the headline scene, the 1M mixed scene and a 1M-triangle
+    Hairball-like scene of long thin diagonal slivers: box and kept pair counts
+    and ms per build, both timed as repeated calls on resident buffers."""
+    import torch
+    from paper_2403_10647_amd import scenes
+    cases = [(args.workload, gin, out)]
+    for name in ("mixed", "hairball"):
+        g = G.GridInput.from_scene(scenes.make_scene(name, seed=args.seed))
+        n, _ = G.count(g, ws)
+        cases.append((name, g, G.build(g, cap_pairs=n, ws=ws)))
+    res = {}
+    for name, g, ref in cases:
+        nbox = ref.npairs
+        plain = G.PlainBuild(g, ref, ws)
+        o, _ = G.build_culled(g, box_cap=nbox, ws=ws)
+        culled = G.CulledBuild(g, o, nbox, ws)
+        row = {"triangles": g.ntris, "box_npairs": nbox}
+        for label, fn in (("plain", plain), ("culled", culled)):
+            fn()
+            torch.cuda.synchronize()
+            G.trace_enable(True)
+            G.trace_read()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            row[f"{label}_ms_per_build"] = round((time.perf_counter() - t0) * 1e3 / reps, 4)
+            k = G.trace_read()
+            G.trace_enable(False)
+            row[f"{label}_kernels"] = {kk: round(v[1] / reps, 4) for kk, v in k.items()}
+        row["kept_npairs"] = o.npairs
+        row["kept_fraction"] = round(o.npairs / max(nbox, 1), 4)
+        row["ms_saved"] = round(row["plain_ms_per_build"] - row["culled_ms_per_build"], 4)
+        res[name] = row
+        del plain, culled, o
+    return res
+
+
 def run_served(G, args, pool, pool_refs, big, big_ref) -> dict:
     """Poisson arrivals of requests drawn from the batch's grids plus the 10M-triangle scene once a
     second, through the continuous-batching server; every output is compared on the device with the
@@ -290,6 +330,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-grid batched build and serving")
     ap.add_argument("--no-serve", action="store_true", help="skip serving")
+    ap.add_argument("--no-culled", action="store_true", help="skip the culled-build comparison")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the per-object pair generation comparison")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
@@ -431,6 +472,9 @@ def main():
             print("# serving", file=sys.stderr, flush=True)
             result["served"] = run_served(G, args, pool, pool_refs, gin, out)
         del pool, pool_refs
+    if not args.no_culled:
+        print("# culled builds", file=sys.stderr, flush=True)
+        result["culled"] = run_culled(G, args, gin, out, ws)
     if not args.no_ablation:
         print("# per-object pair generation", file=sys.stderr, flush=True)
         result["ablation"] = run_ablation(G, args, gin, out, ws)

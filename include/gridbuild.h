@@ -109,6 +109,29 @@ int grid_build(const float *verts_soa, uint32_t nverts, const uint32_t *tris, ui
                const float lo[3], const float hi[3], const uint32_t res[3],
                void *ws, size_t ws_bytes, grid_out *out, void *stream);
 
+/* The whole build with false intersections removed (the fix the Test Results
+ * section proposes for long thin diagonal triangles, Hairball, and the
+ * Conclusions list as future work): a pair <t, c> of triangle t's cell box is
+ * kept only when t touches cell c.  The test is a separating-axis test in grid
+ * coordinates u = (p - lo) * inv, where cell (x, y, z) is the unit box
+ * [x, x+1] x [y, y+1] x [z, z+1]; its axes are the triangle's normal and the
+ * nine cross products of its edges with the grid axes, each bound computed in
+ * a fixed order of FP32 operations, and each cell is widened by 1/64 of a cell
+ * on every side, so rounding may keep a pair the exact test would drop but
+ * never drops one it would keep.  A triangle keeps its whole box when some
+ * vertex coordinate lies outside [0, res] (or is NaN), or when its box holds
+ * at most two cells.  The kept pairs are sorted and ranged as in grid_build.
+ * box_cap bounds the box pair count (grid_count's NO): ws must hold
+ * grid_workspace_size(ntris, box_cap, res) bytes, and out->cap_pairs may be
+ * smaller than box_cap (fewer pairs are kept).  *box_npairs (host) receives
+ * the box pair count and out->npairs the kept count.  GRID_E_CAPACITY when
+ * the box pairs exceed box_cap (out->npairs = 0) or the kept pairs exceed
+ * out->cap_pairs (out->npairs = the kept count).  Synchronizes stream once. */
+int grid_build_culled(const float *verts_soa, uint32_t nverts, const uint32_t *tris, uint32_t ntris,
+                      const float lo[3], const float hi[3], const uint32_t res[3],
+                      void *ws, size_t ws_bytes, uint64_t box_cap, grid_out *out, uint64_t *box_npairs,
+                      void *stream);
+
 /* Object-order pair lists (Algorithm 1, MakeObjectIds through MakeCellIds;
  * Section 3 and GlobalCoords): cells[i], objs[i] for i < NO in object order,
  * each object's cells in GlobalCoords order (x fastest).  Device outputs of

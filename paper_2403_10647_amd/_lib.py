@@ -31,7 +31,7 @@ SCAN_INCLUSIVE_MAX = 1
 SCAN_SEGMENTED_EXCLUSIVE_SUM = 2
 
 EXPORTS = (
-    "grid_strerror", "grid_workspace_size", "grid_count", "grid_build", "grid_build_static", "grid_expand",
+    "grid_strerror", "grid_workspace_size", "grid_count", "grid_build", "grid_build_static", "grid_build_culled", "grid_expand",
     "grid_workspace_size_batched", "grid_count_batched", "grid_build_batched",
     "grid_sort_workspace_size", "grid_sort_pairs", "grid_scan_workspace_size", "grid_scan_u32",
     "grid_trace_enable", "grid_trace_read", "grid_tune_set", "grid_tune_get", "grid_sort_plan",
@@ -86,6 +86,8 @@ def lib():
         L.grid_count.argtypes = [P, U32, P, U32, F3, F3, U3, P, SZ, P, C.POINTER(C.c_uint64), P]
         L.grid_build.argtypes = [P, U32, P, U32, F3, F3, U3, P, SZ, C.POINTER(grid_out), P]
         L.grid_build_static.argtypes = [P, U32, P, U32, F3, F3, U3, C.POINTER(grid_out), P]
+        L.grid_build_culled.argtypes = [P, U32, P, U32, F3, F3, U3, P, SZ, U64, C.POINTER(grid_out),
+                                        C.POINTER(C.c_uint64), P]
         L.grid_expand.argtypes = [P, U32, P, U32, F3, F3, U3, P, SZ, P, P, U64, C.POINTER(C.c_uint64), P]
         L.grid_workspace_size_batched.argtypes = [C.POINTER(grid_desc), U32]
         L.grid_workspace_size_batched.restype = SZ
@@ -113,7 +115,7 @@ def lib():
         L.grid_trace_only.argtypes = [C.c_char_p]
         L.grid_trace_only.restype = C.c_int
         L.grid_trace_read.argtypes = [C.POINTER(grid_trace_entry), C.c_int, C.POINTER(C.c_int)]
-        for name in ("grid_trace_enable", "grid_trace_read", "grid_count", "grid_build", "grid_build_static", "grid_expand", "grid_count_batched", "grid_build_batched",
+        for name in ("grid_trace_enable", "grid_trace_read", "grid_count", "grid_build", "grid_build_static", "grid_build_culled", "grid_expand", "grid_count_batched", "grid_build_batched",
                      "grid_sort_pairs", "grid_scan_u32"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -280,6 +282,28 @@ def build_static(g: GridInput, out: GridResult, stream=None) -> GridResult:
     return out
 
 
+def build_culled(g: GridInput, box_cap: Optional[int] = None, out: Optional[GridResult] = None,
+                 ws: Optional[Workspace] = None, stream=None):
+    """The build with false intersections removed: (GridResult of the kept pairs, box pair count).
+    With no box capacity given, counts first; with no outputs, sizes them for the box pairs."""
+    L = lib()
+    ws = ws or default_workspace(g.verts.device)
+    if box_cap is None:
+        box_cap, _ = count(g, ws, stream=stream)
+    if out is None:
+        dev = g.verts.device
+        out = GridResult(torch.empty(max(box_cap, 1), dtype=torch.int32, device=dev),
+                         torch.empty(max(box_cap, 1), dtype=torch.int32, device=dev),
+                         torch.empty(2 * g.ncells, dtype=torch.int32, device=dev), 0)
+    wp, wn = ws.ptr_size(workspace_size(g.ntris, box_cap, g.res))
+    o = grid_out(out.cells.data_ptr(), out.objs.data_ptr(), out.ranges.data_ptr(), int(out.cells.numel()), 0)
+    nbox = C.c_uint64(0)
+    st = L.grid_build_culled(*_input_args(g), wp, wn, C.c_uint64(box_cap), C.byref(o), C.byref(nbox), _stream(stream))
+    out.npairs = int(o.npairs)
+    _check(st, "grid_build_culled")
+    return out, int(nbox.value)
+
+
 class PlainBuild:
     """grid_build of one input into one output, its C arguments marshalled once.
 
@@ -303,6 +327,28 @@ class PlainBuild:
         if st != GRID_OK:
             raise GridError(st, "grid_build")
         return self.out
+
+
+class CulledBuild:
+    """grid_build_culled of one input into one output, its C arguments marshalled once
+    (the same rules as PlainBuild).  Returns (GridResult, box pair count)."""
+
+    def __init__(self, g: GridInput, out: GridResult, box_cap: int, ws: Optional[Workspace] = None, stream=None):
+        self.g, self.out = g, out
+        self.ws = ws or default_workspace(g.verts.device)
+        wp, wn = self.ws.ptr_size(workspace_size(g.ntris, box_cap, g.res))
+        self._o = grid_out(out.cells.data_ptr(), out.objs.data_ptr(), out.ranges.data_ptr(), int(out.cells.numel()), 0)
+        self._nbox = C.c_uint64(0)
+        self._fn = lib().grid_build_culled
+        self._args = (*_input_args(g), wp, wn, C.c_uint64(box_cap), C.byref(self._o), C.byref(self._nbox),
+                      _stream(stream))
+
+    def __call__(self):
+        st = self._fn(*self._args)
+        self.out.npairs = int(self._o.npairs)
+        if st != GRID_OK:
+            raise GridError(st, "grid_build_culled")
+        return self.out, int(self._nbox.value)
 
 
 def expand(g: GridInput, ws: Optional[Workspace] = None, stream=None):

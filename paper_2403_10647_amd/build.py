@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgridbuild.so")
 SOURCES = ["gridbuild.hip"]
-HEADERS = ["common.hpp", "grid.hpp", "kernels.hpp", "sort.hpp", "ranges.hpp", "scan.hpp"]
+HEADERS = ["common.hpp", "grid.hpp", "kernels.hpp", "sort.hpp", "ranges.hpp", "scan.hpp", "cull.hpp"]
 ARCH = os.environ.get("GRIDBUILD_ARCH", "gfx950")
 
 FLAGS = [

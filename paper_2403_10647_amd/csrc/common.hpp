@@ -25,6 +25,8 @@ struct Control {
   uint32_t error;              // bit 0: bad vertex index
   uint32_t cap_flag;           // set when some grid's NO exceeds its capacity
   uint64_t scratch[4];
+  uint64_t kept;               // culled builds: pairs that survive the overlap test
+  uint64_t box_npairs;         // culled builds: the box pair count (npairs then holds the kept count)
 };
 constexpr uint32_t kErrBadIndex = 1u;
 

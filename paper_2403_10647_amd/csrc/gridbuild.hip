@@ -10,6 +10,7 @@
 #include <mutex>
 #include <vector>
 
+#include "cull.hpp"
 #include "kernels.hpp"
 #include "ranges.hpp"
 #include "scan.hpp"
@@ -168,7 +169,7 @@ Plan make_plan(uint32_t bits, int max_digit = -1) {
 
 // ---- workspace layout -----------------------------------------------------------
 struct Layout {
-  size_t ctl, hist, count_status, zero_end;
+  size_t ctl, hist, count_status, cull_status, zero_end;
   size_t start, box, tfo, tfg, sort_status, keys_alt, vals_alt, keys_alt2, vals_alt2, run, npairs_out, splits,
       tile_grid, table, sink, kmap, ksink, total;
   uint32_t ntfo, ncount_tiles, nsort_tiles_cap, nmerge_tiles_cap;
@@ -190,6 +191,7 @@ Layout make_layout(uint64_t ntris, uint64_t cap_pairs, uint64_t ncells_plus_grid
   L.ctl = take(sizeof(Control));
   L.hist = take(static_cast<size_t>(kHistCopies) * 4 * kRadixMax * sizeof(uint32_t));
   L.count_status = take(std::max<size_t>(L.ncount_tiles, 1) * 8);
+  L.cull_status = take(static_cast<size_t>(L.ntfo) * 8);  // culled builds: one word per expansion tile
   L.zero_end = o;
   L.start = take(ntris * 4);
   L.box = take(ntris * 8);
@@ -274,6 +276,8 @@ struct Build {
   bool batched;
   uint64_t batch_cells;  // batched: cells of all grids (the sort-key space)
   hipStream_t s;
+  bool culled;           // plain builds: false intersections removed before the sort
+  uint64_t out_cap;      // culled builds: pairs the caller's outputs hold
 };
 
 template <bool B>
@@ -354,9 +358,11 @@ int pass_bits(uint32_t width);
 
 // Tile size of radix pass p under the current knobs (a regenerating first pass
 // reads the expansion's tiles; the others take the sort_shape tile).
-uint32_t pass_tile(uint32_t p) {
-  return (g_fused_expand && p == 0) ? static_cast<uint32_t>(kExpandTile)
-                                    : static_cast<uint32_t>(sort_shape_tile(g_sort_shape));
+bool fused_first_pass(const Build& b) { return g_fused_expand != 0 && !b.culled; }
+
+uint32_t pass_tile(const Build& b, uint32_t p) {
+  return (fused_first_pass(b) && p == 0) ? static_cast<uint32_t>(kExpandTile)
+                                         : static_cast<uint32_t>(sort_shape_tile(g_sort_shape));
 }
 
 // The look-back words each radix pass of b's plan will use (kernels built for
@@ -367,7 +373,7 @@ StatusClear status_clear(const Build& b, int RB) {
   c.stride = static_cast<uint64_t>(b.L.nsort_tiles_cap) * (RB > 0 ? (1u << RB) : 1u);
   c.passes = RB > 0 ? b.plan.sp.passes : 0;
   for (uint32_t p = 0; p < c.passes; ++p) {
-    c.tile[p] = pass_tile(p);
+    c.tile[p] = pass_tile(b, p);
     c.radix[p] = 1u << pass_bits(b.plan.sp.width[p]);
   }
   return c;
@@ -408,6 +414,40 @@ int launch_expand(Build& b, uint32_t* cells, uint32_t* objs, uint64_t npairs) {
     kern<<<static_cast<uint32_t>(std::min<uint64_t>(ceil_div(npairs, kExpandTile), 1024)), kExpandBlock, 0, b.s>>>(a);
     GB_LAUNCHED();
   }
+  return GRID_OK;
+}
+
+// Culled builds: the expansion that tests every box pair and keeps the pairs
+// whose triangle touches the cell (into cells/objs, at most dest_cap of them),
+// then the kept count made the build's pair count.
+template <int RB>
+int launch_cull(Build& b, uint32_t* cells, uint32_t* objs, uint64_t dest_cap, uint64_t box_cap) {
+  if (box_cap > 0) {
+    if (!cells || !objs) return GRID_E_INVAL;
+    CullArgs a{};
+    a.o.ex = expand_args(b);
+    a.o.cells = cells;
+    a.o.objs = objs;
+    a.o.plan = b.plan.sp;
+    a.o.hist = at<uint32_t>(b.ws, b.L.hist);
+    a.o.clear = status_clear(b, RB);
+    a.o.ctl = at<Control>(b.ws, b.L.ctl);
+    a.dest_cap = dest_cap;
+    a.status = at<uint64_t>(b.ws, b.L.cull_status);
+    TraceScope ts(b.s, RB > 0 ? "expand_cull_hist" : "expand_cull");
+    auto kern = expand_cull_kernel<kExpandBlock, kExpandK, RB>;
+    kern<<<resident_blocks(kern, kExpandBlock, ceil_div(box_cap, kExpandTile)), kExpandBlock, 0, b.s>>>(a);
+    GB_LAUNCHED();
+  }
+  CullCommitArgs c{};
+  c.ctl = at<Control>(b.ws, b.L.ctl);
+  c.run = at<GridRun>(b.ws, b.L.run);
+  c.out_cap = b.out_cap;
+  c.ncells = ncells_of(b.gs.one.res);
+  c.merge_tile = kMergeTile;
+  TraceScope ts(b.s, "cull_commit");
+  cull_commit_kernel<<<1, kWave, 0, b.s>>>(c);
+  GB_LAUNCHED();
   return GRID_OK;
 }
 
@@ -510,7 +550,7 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
   const uint32_t ntiles = static_cast<uint32_t>(ceil_div(npairs, kExpandTile));
   Control* ctl = at<Control>(b.ws, b.L.ctl);
   const uint32_t P = sp.passes;
-  const bool fused = g_fused_expand != 0;
+  const bool fused = fused_first_pass(b);
   const uint32_t* in_k = nullptr;
   const uint32_t* in_v = nullptr;
   if (fused) {
@@ -526,7 +566,14 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
     GB_LAUNCHED();
   } else {
     const Dest d = sort_dest(b, B, -1, P, out_cells, out_objs);
-    int st = launch_expand<RB, B>(b, d.k, d.v, npairs);
+    int st;
+    if (!B && b.culled) {
+      // the kept pairs go where the expansion's would: the caller's arrays or the workspace's
+      const uint64_t dest_cap = d.k == out_cells ? b.out_cap : npairs;
+      st = launch_cull<RB>(b, d.k, d.v, dest_cap, npairs);
+    } else {
+      st = launch_expand<RB, B>(b, d.k, d.v, npairs);
+    }
     if (st) return st;
     in_k = d.k;
     in_v = d.v;
@@ -559,7 +606,7 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
     }
     a.ctl = ctl;
     const bool regen = fused && p == 0;
-    const uint32_t pass_tiles = static_cast<uint32_t>(ceil_div(npairs, pass_tile(p)));
+    const uint32_t pass_tiles = static_cast<uint32_t>(ceil_div(npairs, pass_tile(b, p)));
     TraceScope ts(b.s, regen ? "onesweep_expand" : (B && last) ? "onesweep_grids" : "onesweep");
     int st = launch_pass<B>(a, pass_bits(sp.width[p]), regen, B && last, pass_tiles, b.s);
     if (st) return st;
@@ -616,6 +663,7 @@ struct HostCtl {
   uint64_t npairs;
   uint32_t error;
   uint32_t cap_flag;
+  uint64_t box_npairs;
 };
 
 int read_ctl(const Build& b, HostCtl* h) {
@@ -625,6 +673,7 @@ int read_ctl(const Build& b, HostCtl* h) {
   h->npairs = c.npairs;
   h->error = c.error;
   h->cap_flag = c.cap_flag;
+  h->box_npairs = c.box_npairs;
   return GRID_OK;
 }
 
@@ -730,6 +779,44 @@ int grid_build(const float* verts_soa, uint32_t nverts, const uint32_t* tris, ui
   if (h.error & kErrBadIndex) return GRID_E_BADINDEX;
   if (h.npairs > 0xFFFFFFFFull) return GRID_E_OVERFLOW;
   if (h.npairs > cap) return GRID_E_CAPACITY;
+  return GRID_OK;
+}
+
+int grid_build_culled(const float* verts_soa, uint32_t nverts, const uint32_t* tris, uint32_t ntris,
+                      const float lo[3], const float hi[3], const uint32_t res[3], void* ws, size_t ws_bytes,
+                      uint64_t box_cap, grid_out* out, uint64_t* box_npairs, void* stream) {
+  if (!out || !box_npairs || !out->ranges) return GRID_E_INVAL;
+  if (box_cap > 0 && (!out->cells || !out->objs)) return GRID_E_INVAL;
+  Build b{};
+  // the layout (expansion tiles, workspace pair buffers) is sized for the box pairs
+  int st = prepare_plain(b, verts_soa, nverts, tris, ntris, lo, hi, res, ws, ws_bytes, box_cap,
+                         static_cast<hipStream_t>(stream));
+  if (st) return st;
+  b.culled = true;
+  b.out_cap = out->cap_pairs;
+  b.gs.one.out_cells = out->cells;
+  b.gs.one.out_objs = out->objs;
+  b.gs.one.out_ranges = out->ranges;
+  if ((st = launch_zero(b.ws, b.L.zero_end, b.s))) return st;
+  if ((st = launch_count<false>(b))) return st;
+  if ((st = launch_plan<false>(b))) return st;  // checks the box pairs against box_cap
+  if (b.plan.sp.passes == 0 || box_cap == 0) {
+    if ((st = launch_cull<0>(b, out->cells, out->objs, out->cap_pairs, box_cap))) return st;
+  } else {
+    if ((st = launch_sort<false>(b, out->cells, out->objs, box_cap))) return st;
+  }
+  if ((st = launch_ranges<false>(b, ncells_of(res) + 1 + std::min(box_cap, out->cap_pairs)))) return st;
+  HostCtl h{};
+  if ((st = read_ctl(b, &h))) return st;
+  if (h.error & kErrBadIndex) return GRID_E_BADINDEX;
+  *box_npairs = h.box_npairs;
+  if (h.box_npairs > 0xFFFFFFFFull) return GRID_E_OVERFLOW;
+  if (h.box_npairs > box_cap) {  // nothing was kept: the box pairs did not fit the workspace
+    out->npairs = 0;
+    return GRID_E_CAPACITY;
+  }
+  out->npairs = h.npairs;
+  if (h.npairs > out->cap_pairs) return GRID_E_CAPACITY;
   return GRID_OK;
 }
 

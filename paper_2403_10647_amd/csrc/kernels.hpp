@@ -334,9 +334,11 @@ GB_DEV uint32_t item_slot(uint32_t tid, int k) {
 
 // s_slot must hold padded(Block * K) words.  Returns the tile's item count.
 // OneGrid: the caller guarantees that the tile's objects lie in one grid.
+// coords (optional, blocked single-grid tiles only): each item's cell
+// coordinates packed as x | y << 10 | z << 20.
 template <int Block, int K, bool Batched, int Layout = kStriped, bool OneGrid = false>
 GB_DEV uint32_t expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs, uint32_t ntiles, uint32_t* s_slot,
-                            uint32_t* s_wtot, uint32_t (&keys)[K], uint32_t (&vals)[K]) {
+                            uint32_t* s_wtot, uint32_t (&keys)[K], uint32_t (&vals)[K], uint32_t* coords = nullptr) {
   constexpr int N = Block * K;
   static_assert(N <= 65536, "slot and object offsets are packed in 16 bits");
   constexpr int kHeadBatch = 4;
@@ -431,6 +433,7 @@ GB_DEV uint32_t expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs,
       }
       const GridKeyParams& gp = tg.p;
       const uint32_t cell = (b.lo[0] + x) + gp.res0 * (b.lo[1] + y) + gp.res01 * (b.lo[2] + z);
+      if (coords) coords[k] = (b.lo[0] + x) | ((b.lo[1] + y) << 10) | ((b.lo[2] + z) << 20);
       if constexpr (Batched) {
         keys[k] = gp.cell_base + cell;
         vals[k] = obj - gp.tri_base;

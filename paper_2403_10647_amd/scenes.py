@@ -13,6 +13,10 @@ none of them are available here, so these generators stand in for them:
   the size class of the paper's 10M-triangle real-time claim (abstract).
 * ``batch``  - 512 independent ``mixed``-style grids with log-uniform
   triangle counts in [1e3, 2e5].
+* ``hairball`` - long, thin, diagonal slivers (strands of random direction,
+  lengths log-uniform in [0.3, 3], widths near 1% of the length) in a
+  [0, 10]^3 box: the shape of the paper's Hairball scene, whose triangles'
+  boxes hold many cells the triangles never touch (Test Results).
 
 This module holds no part of the grid-building arithmetic: it only draws
 vertices, picks the grid bounds (the vertices' FP32 bounding box) and the grid
@@ -33,8 +37,8 @@ __all__ = [
     "resolution_rule", "aabb_bounds", "SCENE_NAMES",
 ]
 
-SCENE_NAMES = ("small", "mixed", "arch", "batch")
-_STREAM = {"small": 0, "mixed": 1, "arch": 2, "batch": 3, "serve": 4}
+SCENE_NAMES = ("small", "mixed", "arch", "batch", "hairball")
+_STREAM = {"small": 0, "mixed": 1, "arch": 2, "batch": 3, "serve": 4, "hairball": 5}
 
 
 @dataclasses.dataclass
@@ -205,6 +209,22 @@ def make_batch(seed: int = 0, ngrids: int = 512, sizes: Optional[np.ndarray] = N
     return out
 
 
+def _hairball_scene(seed: int, ntris: int = 1_000_000, lam: float = 4.0, cap: int = 512) -> Scene:
+    """Slivers: vertex a uniform in the box, b = a + L d (L log-uniform in
+    [0.3, 3], d uniform on the sphere), c = b + w e with e a unit vector and w
+    log-uniform in [0.003, 0.03]."""
+    rng = _rng(seed, _STREAM["hairball"])
+    a = rng.uniform(0.0, 10.0, size=(ntris, 3))
+    length = np.exp(rng.uniform(math.log(0.3), math.log(3.0), size=(ntris, 1)))
+    b = a + length * _unit_sphere(rng, (ntris,))
+    w = np.exp(rng.uniform(math.log(0.003), math.log(0.03), size=(ntris, 1)))
+    c = b + w * _unit_sphere(rng, (ntris,))
+    v = np.stack([a, b, c], axis=1)
+    verts, tris = soup_from_vertices(v)
+    lo, hi = aabb_bounds(verts)
+    return Scene("hairball", verts, tris, lo, hi, resolution_rule(lo, hi, ntris, lam, cap), seed)
+
+
 def make_scene(name: str, seed: int = 0, ntris: Optional[int] = None) -> Scene:
     """Build one of the named single-grid scenes (``ntris`` rescales it for tests)."""
     if name == "small":
@@ -216,4 +236,6 @@ def make_scene(name: str, seed: int = 0, ntris: Optional[int] = None) -> Scene:
             return _arch_scene(seed)
         nwalls = max(2, ntris // 1000)
         return _arch_scene(seed, ntris, nwalls=nwalls, nclusters=max(1, ntris // 5000))
-    raise ValueError(f"unknown scene {name!r}; expected one of {SCENE_NAMES[:3]}")
+    if name == "hairball":
+        return _hairball_scene(seed, ntris or 1_000_000)
+    raise ValueError(f"unknown scene {name!r}; expected one of small, mixed, arch, hairball")

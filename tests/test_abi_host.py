@@ -215,3 +215,20 @@ def test_static_build_rejects_oversize_before_device_work(G):
     assert L.grid_build_static(None, 0, None, 0, G._f3([0, 0, 0]), G._f3([1, 1, 1]), bad, C.byref(o), None) \
         == G.GRID_E_INVAL
     assert L.grid_build_static(None, 0, None, 0, G._f3([0, 0, 0]), G._f3([1, 1, 1]), res, None, None) == G.GRID_E_INVAL
+
+
+def test_culled_build_argument_checks(G):
+    """grid_build_culled rejects null outputs, a null box-count pointer and bad
+    grids before any device work."""
+    L = G.lib()
+    res = G._u3([4, 4, 4])
+    lo, hi = G._f3([0, 0, 0]), G._f3([1, 1, 1])
+    nb = C.c_uint64(0)
+    o = G.grid_out(None, None, 1, 0, 0)
+    assert L.grid_build_culled(None, 0, None, 0, lo, hi, res, None, 0, 0, None, C.byref(nb), None) == G.GRID_E_INVAL
+    assert L.grid_build_culled(None, 0, None, 0, lo, hi, res, None, 0, 0, C.byref(o), None, None) == G.GRID_E_INVAL
+    # a box capacity with no pair arrays to write the kept pairs into
+    assert L.grid_build_culled(None, 0, None, 0, lo, hi, res, None, 0, 10, C.byref(o), C.byref(nb), None) \
+        == G.GRID_E_INVAL
+    assert L.grid_build_culled(None, 0, None, 0, lo, hi, G._u3([0, 4, 4]), None, 0, 0, C.byref(o), C.byref(nb),
+                               None) == G.GRID_E_INVAL

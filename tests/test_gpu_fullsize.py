@@ -66,3 +66,26 @@ def test_batch_512_full(G):
         c, o, rg = r.numpy()
         oc, oo, orr = oracle.build(s.verts, s.tris, s.lo, s.hi, s.res)
         assert np.array_equal(c, oc) and np.array_equal(o, oo) and np.array_equal(rg, orr), i
+
+
+def _full_culled(G, s):
+    g = G.GridInput.from_scene(s)
+    ws = G.Workspace()
+    nbox, _ = G.count(g, ws)
+    out, nb = G.build_culled(g, box_cap=nbox, ws=ws)
+    out, nb = G.build_culled(g, box_cap=nbox, ws=ws, out=out)   # repeated into one output
+    c, o, r = out.numpy()
+    _say("oracle culled", s.name, s.ntris, nbox, out.npairs)
+    oc, oo, orr, obox = oracle.build_scene_culled(s)
+    assert nb == obox == nbox and out.npairs == len(oc)
+    assert np.array_equal(c, oc) and np.array_equal(o, oo) and np.array_equal(r, orr)
+    assert r[0] == 0 and r[-1] == out.npairs and np.all(r[1:-1:2] == r[2::2])
+    return nbox, out.npairs
+
+
+@pytest.mark.parametrize("name", ["mixed", "hairball", "arch"])
+def test_culled_full(G, name):
+    s = scenes.make_scene(name, seed=0)
+    _say(name, s.ntris, list(s.res))
+    nbox, kept = _full_culled(G, s)
+    assert 0 < kept < nbox
