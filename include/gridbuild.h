@@ -60,7 +60,8 @@ typedef enum grid_status {
   GRID_E_OVERFLOW = -3,  /* NO > 2^32 - 1 */
   GRID_E_CAPACITY = -4,  /* NO > cap_pairs; npairs holds the required count */
   GRID_E_BADINDEX = -5,  /* a triangle references a vertex index >= nverts */
-  GRID_E_HIP = -6        /* a HIP runtime call failed */
+  GRID_E_HIP = -6,       /* a HIP runtime call failed */
+  GRID_E_INTERNAL = -7   /* an internal consistency check on the device failed; outputs are invalid */
 } grid_status;
 
 /* Output of one grid.  cells/objs/ranges are device pointers owned by the caller. */

@@ -25,6 +25,7 @@ GRID_E_OVERFLOW = -3
 GRID_E_CAPACITY = -4
 GRID_E_BADINDEX = -5
 GRID_E_HIP = -6
+GRID_E_INTERNAL = -7
 
 SCAN_EXCLUSIVE_SUM = 0
 SCAN_INCLUSIVE_MAX = 1

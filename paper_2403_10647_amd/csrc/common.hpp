@@ -27,8 +27,11 @@ struct Control {
   uint64_t scratch[4];
   uint64_t kept;               // culled builds: pairs that survive the overlap test
   uint64_t box_npairs;         // culled builds: the box pair count (npairs then holds the kept count)
+  uint32_t tfo_work_n;         // tile-owner runs left for the plan kernel to write
+  uint32_t pad;
 };
 constexpr uint32_t kErrBadIndex = 1u;
+constexpr uint32_t kErrInternal = 2u;  // an internal consistency check failed (the build's output is invalid)
 
 // After the count, a build whose inputs were rejected on the device (a bad
 // vertex index, a pair count above capacity) writes nothing more: every later

@@ -84,15 +84,17 @@ GB_DEV void cull_axes(const float u[3][3], CullAxes& c) {
 GB_DEV bool cull_touches(const CullAxes& c, float x, float y, float z) {
   const float b[3] = {x, y, z};
   const float cn = dot3f(c.n, b);
-  bool sep = cn > c.n_above || cn < c.n_below;
+  // every axis is evaluated (no early exit): the result is the same, and the
+  // wave does not branch per axis
+  bool sep = (cn > c.n_above) | (cn < c.n_below);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const float cx = __fadd_rn(__fmul_rn(c.e[3 * i + 0][0], y), __fmul_rn(c.e[3 * i + 0][1], z));
     const float cy = __fadd_rn(__fmul_rn(c.e[3 * i + 1][0], x), __fmul_rn(c.e[3 * i + 1][1], z));
     const float cz = __fadd_rn(__fmul_rn(c.e[3 * i + 2][0], x), __fmul_rn(c.e[3 * i + 2][1], y));
-    sep = sep || cx > c.e_above[3 * i + 0] || cx < c.e_below[3 * i + 0];
-    sep = sep || cy > c.e_above[3 * i + 1] || cy < c.e_below[3 * i + 1];
-    sep = sep || cz > c.e_above[3 * i + 2] || cz < c.e_below[3 * i + 2];
+    sep = sep | (cx > c.e_above[3 * i + 0]) | (cx < c.e_below[3 * i + 0]);
+    sep = sep | (cy > c.e_above[3 * i + 1]) | (cy < c.e_below[3 * i + 1]);
+    sep = sep | (cz > c.e_above[3 * i + 2]) | (cz < c.e_below[3 * i + 2]);
   }
   return !sep;
 }

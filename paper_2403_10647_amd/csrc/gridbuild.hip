@@ -168,9 +168,13 @@ Plan make_plan(uint32_t bits, int max_digit = -1) {
 }
 
 // ---- workspace layout -----------------------------------------------------------
+// Tile-owner runs the count can leave to the plan kernel: each run is more
+// than kTfoInline entries of the table.
+uint32_t tfo_work_cap(uint32_t ntfo) { return ntfo / kTfoInline + 2; }
+
 struct Layout {
   size_t ctl, hist, count_status, cull_status, zero_end;
-  size_t start, box, tfo, tfg, sort_status, keys_alt, vals_alt, keys_alt2, vals_alt2, run, npairs_out, splits,
+  size_t start, box, tfo, tfg, tfo_work, sort_status, keys_alt, vals_alt, keys_alt2, vals_alt2, run, npairs_out, splits,
       tile_grid, table, sink, kmap, ksink, total;
   uint32_t ntfo, ncount_tiles, nsort_tiles_cap, nmerge_tiles_cap;
 };
@@ -197,6 +201,7 @@ Layout make_layout(uint64_t ntris, uint64_t cap_pairs, uint64_t ncells_plus_grid
   L.box = take(ntris * 8);
   L.tfo = take(static_cast<size_t>(L.ntfo) * 4);
   L.tfg = take(batched ? static_cast<size_t>(L.ntfo) * 4 : 0);
+  L.tfo_work = take(tfo_work_cap(L.ntfo) * sizeof(uint4));
   L.sort_status = take(static_cast<size_t>(plan.sp.passes) * L.nsort_tiles_cap * (size_t{1} << plan.rb) * 8);
   L.keys_alt = take(cap_pairs * 4);
   L.vals_alt = take(cap_pairs * 4);
@@ -293,6 +298,8 @@ int launch_count(Build& b) {
   a.ntfo = b.L.ntfo;
   a.tile_shift = kExpandTileShift;
   a.status = at<uint64_t>(b.ws, b.L.count_status);
+  a.tfo_work = at<uint4>(b.ws, b.L.tfo_work);
+  a.tfo_work_cap = tfo_work_cap(b.L.ntfo);
   a.ctl = at<Control>(b.ws, b.L.ctl);
   TraceScope ts(b.s, "count_scan");
   count_kernel<kCountBlock, kCountK, B><<<b.L.ncount_tiles, kCountBlock, 0, b.s>>>(a);
@@ -310,6 +317,10 @@ int launch_plan(Build& b) {
   a.run = at<GridRun>(b.ws, b.L.run);
   a.npairs_out = at<uint64_t>(b.ws, b.L.npairs_out);
   a.cap_flag = &at<Control>(b.ws, b.L.ctl)->cap_flag;
+  a.tfo = at<uint32_t>(b.ws, b.L.tfo);
+  a.tfg = at<uint32_t>(b.ws, b.L.tfg);
+  a.tfo_work = at<uint4>(b.ws, b.L.tfo_work);
+  a.tfo_work_cap = tfo_work_cap(b.L.ntfo);
   a.ctl = at<Control>(b.ws, b.L.ctl);
   TraceScope ts(b.s, "plan");
   plan_kernel<kPlanBlock, B><<<1, kPlanBlock, 0, b.s>>>(a);
@@ -325,6 +336,7 @@ ExpandArgs expand_args(const Build& b) {
   e.tfo = at<uint32_t>(b.ws, b.L.tfo);
   e.tfg = at<uint32_t>(b.ws, b.L.tfg);
   e.ntris = b.ntris;
+  e.ctl = at<Control>(b.ws, b.L.ctl);
   return e;
 }
 
@@ -666,6 +678,13 @@ struct HostCtl {
   uint64_t box_npairs;
 };
 
+// Status of the device-side error bits (0 when none is set).
+int device_error(uint32_t error) {
+  if (error & kErrBadIndex) return GRID_E_BADINDEX;
+  if (error & kErrInternal) return GRID_E_INTERNAL;
+  return GRID_OK;
+}
+
 int read_ctl(const Build& b, HostCtl* h) {
   Control c;
   GB_TRY(hipMemcpyAsync(&c, at<Control>(b.ws, b.L.ctl), sizeof(Control), hipMemcpyDeviceToHost, b.s));
@@ -704,7 +723,7 @@ int count_phase_plain(Build& b, HostCtl* h) {
   if (st) return st;
   if ((st = launch_count<false>(b))) return st;
   if ((st = read_ctl(b, h))) return st;
-  if (h->error & kErrBadIndex) return GRID_E_BADINDEX;
+  if (h->error) return device_error(h->error);
   if (h->npairs > 0xFFFFFFFFull) return GRID_E_OVERFLOW;
   return GRID_OK;
 }
@@ -722,6 +741,7 @@ const char* grid_strerror(int status) {
     case GRID_E_CAPACITY: return "pair capacity too small";
     case GRID_E_BADINDEX: return "vertex index out of range";
     case GRID_E_HIP: return "HIP runtime error";
+    case GRID_E_INTERNAL: return "internal consistency check failed";
     default: return "unknown status";
   }
 }
@@ -776,7 +796,7 @@ int grid_build(const float* verts_soa, uint32_t nverts, const uint32_t* tris, ui
   HostCtl h{};
   if ((st = read_ctl(b, &h))) return st;
   out->npairs = h.npairs;
-  if (h.error & kErrBadIndex) return GRID_E_BADINDEX;
+  if (h.error) return device_error(h.error);
   if (h.npairs > 0xFFFFFFFFull) return GRID_E_OVERFLOW;
   if (h.npairs > cap) return GRID_E_CAPACITY;
   return GRID_OK;
@@ -808,7 +828,7 @@ int grid_build_culled(const float* verts_soa, uint32_t nverts, const uint32_t* t
   if ((st = launch_ranges<false>(b, ncells_of(res) + 1 + std::min(box_cap, out->cap_pairs)))) return st;
   HostCtl h{};
   if ((st = read_ctl(b, &h))) return st;
-  if (h.error & kErrBadIndex) return GRID_E_BADINDEX;
+  if (h.error) return device_error(h.error);
   *box_npairs = h.box_npairs;
   if (h.box_npairs > 0xFFFFFFFFull) return GRID_E_OVERFLOW;
   if (h.box_npairs > box_cap) {  // nothing was kept: the box pairs did not fit the workspace
@@ -833,6 +853,7 @@ int grid_expand(const float* verts_soa, uint32_t nverts, const uint32_t* tris, u
   *npairs = h.npairs;
   if (st) return st;
   if (h.npairs > cap_pairs) return GRID_E_CAPACITY;
+  if ((st = launch_plan<false>(b))) return st;  // the tile-owner runs of huge objects
   if ((st = launch_expand<0, false>(b, cells, objs, h.npairs))) return st;
   GB_TRY(hipStreamSynchronize(b.s));
   return GRID_OK;
@@ -978,7 +999,7 @@ int count_phase_batched(Build& b, uint32_t ngrids, std::vector<uint64_t>& npairs
   npairs.resize(ngrids);
   GB_TRY(hipMemcpyAsync(npairs.data(), at<uint64_t>(b.ws, b.L.npairs_out), ngrids * 8, hipMemcpyDeviceToHost, b.s));
   if ((st = read_ctl(b, h))) return st;
-  if (h->error & kErrBadIndex) return GRID_E_BADINDEX;
+  if (h->error) return device_error(h->error);
   if (h->npairs > 0xFFFFFFFFull) return GRID_E_OVERFLOW;
   return GRID_OK;
 }
@@ -1347,7 +1368,7 @@ int grid_workspace_status(const void* ws, uint64_t* npairs_total, void* stream) 
   GB_TRY(hipMemcpyAsync(&c, ws, sizeof(Control), hipMemcpyDeviceToHost, s));
   GB_TRY(hipStreamSynchronize(s));
   if (npairs_total) *npairs_total = c.npairs;
-  if (c.error & kErrBadIndex) return GRID_E_BADINDEX;
+  if (c.error) return device_error(c.error);
   if (c.cap_flag & 2u) return GRID_E_OVERFLOW;
   if (c.cap_flag & 1u) return GRID_E_CAPACITY;
   return GRID_OK;

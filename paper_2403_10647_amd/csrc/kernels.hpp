@@ -75,8 +75,15 @@ struct CountArgs {
   uint32_t ntfo;
   uint32_t tile_shift;      // log2 of the expansion tile size (one tfo entry per expansion tile)
   uint64_t* status;         // [count tiles] look-back words
+  uint4* tfo_work;          // [tfo_work_cap] (object, grid, first entry, last entry) runs left for the plan kernel
+  uint32_t tfo_work_cap;
   Control* ctl;
 };
+
+// Tile-owner entries the count writes per object; an object that owns the
+// first pair of more expansion tiles leaves the rest to the plan kernel, whose
+// whole workgroup writes them, so no thread writes more than this many.
+constexpr uint32_t kTfoInline = 32;
 
 // Grid of triangle t (largest g with tri_base[g] <= t), found by one whole
 // wave: each level probes 64 evenly spaced grids of the remaining range at
@@ -229,9 +236,18 @@ __global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
         // about one object per expansion tile; its grid is the tile's first
         // or one a few entries after it
         const uint32_t g = one ? gl : grid_of_tri<Batched>(a.gs, static_cast<uint32_t>(t), gl);
-        for (; j <= jlast && j < a.ntfo; ++j) {
+        const uint64_t jend = jlast < a.ntfo ? jlast : a.ntfo - 1;
+        const uint64_t jin = j + kTfoInline - 1 < jend ? j + kTfoInline - 1 : jend;
+        for (; j <= jin; ++j) {
           a.tfo[j] = static_cast<uint32_t>(t);
           if constexpr (Batched) a.tfg[j] = g;
+        }
+        if (j <= jend) {  // a huge object: the rest of its run goes to the plan kernel
+          const uint32_t w = atomicAdd(&a.ctl->tfo_work_n, 1u);
+          if (w < a.tfo_work_cap)
+            a.tfo_work[w] = make_uint4(static_cast<uint32_t>(t), g, static_cast<uint32_t>(j), static_cast<uint32_t>(jend));
+          else
+            atomicOr(&a.ctl->error, kErrInternal);
         }
       }
     }
@@ -265,6 +281,7 @@ struct ExpandArgs {
   const uint32_t* tfo;      // [ntiles + ...] owner of each tile's first pair
   const uint32_t* tfg;      // batched: grid of that owner
   uint32_t ntris;           // total triangles
+  Control* ctl;             // for the consistency flag
 };
 
 // What the expansion needs of a triangle's grid to form its keys and values.
@@ -346,7 +363,13 @@ GB_DEV uint32_t expand_tile(const ExpandArgs& a, uint32_t tile, uint64_t npairs,
   const uint64_t base = static_cast<uint64_t>(tile) * N;
   const uint32_t n = static_cast<uint32_t>(npairs - base < N ? npairs - base : N);
   const uint32_t t0 = a.tfo[tile];
-  const uint32_t thi = tile + 1 < ntiles ? a.tfo[tile + 1] : a.ntris - 1;
+  uint32_t thi = tile + 1 < ntiles ? a.tfo[tile + 1] : a.ntris - 1;
+  if (thi < t0) {
+    // tile owners must not decrease; if they did, the build reports an internal
+    // error and this tile stays within its own first object
+    if (threadIdx.x == 0) atomicOr(&a.ctl->error, kErrInternal);
+    thi = t0;
+  }
   const uint32_t s0 = a.start[t0];  // the carried-in owner starts at or before the tile
 #pragma unroll
   for (int k = 0; k < K; ++k) s_slot[pad32(k * Block + tid)] = 0;

@@ -31,12 +31,27 @@ struct PlanArgs {
   GridRun* run;            // [ngrids + 1]; run[ngrids].mtile_base = total merge tiles
   uint64_t* npairs_out;    // [ngrids] copy of each grid's NO for the host
   uint32_t* cap_flag;      // set when a grid's NO exceeds its capacity
+  uint32_t* tfo;           // tile-owner table of the expansion (and tfg, batched) ...
+  uint32_t* tfg;
+  const uint4* tfo_work;   // ... and the runs of it the count left for this kernel
+  uint32_t tfo_work_cap;
   Control* ctl;
 };
 
 template <int Block, bool Batched>
 __global__ __launch_bounds__(Block) void plan_kernel(PlanArgs a) {
   __shared__ uint32_t s_wtot[Block / kWave];
+  {
+    // the tile-owner runs of huge objects, written by the whole workgroup
+    const uint32_t nw = a.ctl->tfo_work_n < a.tfo_work_cap ? a.ctl->tfo_work_n : a.tfo_work_cap;
+    for (uint32_t w = 0; w < nw; ++w) {
+      const uint4 it = a.tfo_work[w];
+      for (uint32_t j = it.z + threadIdx.x; j <= it.w; j += Block) {
+        a.tfo[j] = it.x;
+        if constexpr (Batched) a.tfg[j] = it.y;
+      }
+    }
+  }
   const uint64_t total = a.ctl->npairs;
   const uint32_t G = a.gs.ngrids;
   if (threadIdx.x == 0 && total > 0xFFFFFFFFull) atomicOr(a.cap_flag, 2u);  // 32-bit pair indices overflow

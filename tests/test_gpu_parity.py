@@ -341,3 +341,24 @@ def test_plain_build_object_repeats(G):
             assert np.array_equal(x, y)
     oc, oo, orr = oracle.build_scene(s)
     assert np.array_equal(ref[0], oc) and np.array_equal(ref[1], oo) and np.array_equal(ref[2], orr)
+
+
+@pytest.mark.parametrize("res", [(512, 512, 1), (1024, 1024, 4)])
+def test_huge_triangles_tile_owner_runs(G, res):
+    # triangles whose boxes span hundreds of expansion tiles: the count writes
+    # the first few tile owners of each, the plan kernel the rest
+    rng = np.random.default_rng(11)
+    big = [[[0.01, 0.01, 0.01], [0.99, 0.02, 0.98], [0.5, 0.99, 0.5]],
+           [[0.98, 0.97, 0.2], [0.03, 0.5, 0.9], [0.6, 0.02, 0.4]]]
+    small = rng.uniform(0.0, 1.0, size=(3000, 1, 3)) + rng.uniform(-0.004, 0.004, size=(3000, 3, 3))
+    v = np.concatenate([np.asarray(big, np.float64), small, np.asarray(big, np.float64)[::-1]], axis=0)
+    verts, tris = scenes.soup_from_vertices(v)
+    s = _scene(verts, tris, [0, 0, 0], [1, 1, 1], res, name=f"huge-{res}")
+    _check_build(G, s)
+    # the same grid inside a batch, between two ordinary grids
+    batch = [scenes.make_scene("small", seed=3), s, scenes.make_scene("small", seed=4)]
+    outs = G.build_batched([G.GridInput.from_scene(x) for x in batch])
+    for r, x in zip(outs, batch):
+        c, o, rg = r.numpy()
+        oc, oo, orr = oracle.build_scene(x)
+        assert np.array_equal(c, oc) and np.array_equal(o, oo) and np.array_equal(rg, orr), x.name
