@@ -47,6 +47,14 @@ def kernel_bytes(name: str, T: int, NO: int, R: int) -> float:
     }.get(name, 0.0)
 
 
+def survey_bytes(T: int, NO: int, R: int, passes: int) -> int:
+    """The survey's per-build byte model at the radix passes the build runs:
+    80 T + (16 + 16 P) NO + 8 R (inputs, count/start and box round trips, the
+    expansion's pairs, one histogram read, P passes that read and write key and
+    value, the range pass's read of the sorted cells, and the range table)."""
+    return 80 * T + (16 + 16 * passes) * NO + 8 * R
+
+
 def source_hash() -> str:
     """Hash of the kernel sources' code (comments and whitespace left out), which
     ties the committed traffic counters to the kernels they were taken on."""
@@ -83,15 +91,19 @@ def cpu_baseline(scene, gpu_out) -> dict:
     import numpy as np
     import oracle
     no = oracle.probe_npairs(scene.verts, scene.tris, scene.lo, scene.hi, scene.res)  # sizes the oracle's output
-    t0 = time.perf_counter()
-    c, o, r = oracle.build(scene.verts, scene.tris, scene.lo, scene.hi, scene.res, npairs=no)
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(3):   # the median of three whole serial builds
+        t0 = time.perf_counter()
+        c, o, r = oracle.build(scene.verts, scene.tris, scene.lo, scene.hi, scene.res, npairs=no)
+        times.append(time.perf_counter() - t0)
+    dt = sorted(times)[1]
     npairs = int(no)
     gc, go, gr = gpu_out.numpy()
     same = bool(gpu_out.npairs == npairs and np.array_equal(c, gc) and np.array_equal(o, go) and np.array_equal(r, gr))
     return {"value": round(npairs / dt / 1e6, 3), "unit": "Mpairs/s", "cores": 1, "kind": "oracle",
-            "sample": f"the full workload, one serial build ({scene.ntris} triangles, {npairs} pairs) "
-                      f"in {dt:.2f} s on {platform.processor() or platform.machine()}, {os.cpu_count()} host cores",
+            "sample": f"the full workload, median of three serial builds ({scene.ntris} triangles, {npairs} pairs): "
+                      f"{dt:.2f} s (runs {', '.join(f'{x:.2f}' for x in times)} s) on "
+                      f"{platform.processor() or platform.machine()}, {os.cpu_count()} host cores",
             "gpu_grid_identical": same}
 
 
@@ -113,6 +125,53 @@ def run_copy(steps: int):
     print(json.dumps({"mode": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
                       "launches": steps + 1, "ms_per_copy": round(ms, 4),
                       "GBps_read_plus_write": round(8 * n / (ms * 1e-3) / 1e9, 1)}), flush=True)
+
+
+def run_configs(G, args, steps: int = 20) -> dict:
+    """The other single-grid configurations: the 4096-triangle scene (launch
+    bound: microseconds per build) and the 1M mixed scene (ms per build,
+    Mpairs/s, the dominant kernel's roofline and the survey model's fraction)."""
+    import torch
+    from paper_2403_10647_amd import scenes
+    res = {}
+    for name in ("small", "mixed"):
+        s = scenes.make_scene(name, seed=args.seed)
+        g = G.GridInput.from_scene(s)
+        ws = G.Workspace()
+        n, _ = G.count(g, ws)
+        out = G.build(g, cap_pairs=n, ws=ws)
+        b = G.PlainBuild(g, out, ws)
+        for _ in range(3):
+            b()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        G.trace_enable(True)
+        G.trace_read()
+        for _ in range(steps):
+            b()
+        k = G.trace_read()
+        G.trace_enable(False)
+        T, R = s.ntris, s.ncells
+        dom = max(k, key=lambda x: k[x][1])
+        avg = k[dom][1] / k[dom][0]
+        bpl = kernel_bytes(dom, T, n, R)
+        passes = G.sort_plan(max(0, (R - 1).bit_length()))[0]
+        bs = survey_bytes(T, n, R, passes)
+        res[name] = {"triangles": T, "npairs": n, "cells": R, "ms_per_build": round(ms, 4),
+                     "us_per_build": round(ms * 1e3, 1), "Mpairs_per_s": round(n / (ms * 1e-3) / 1e6, 1),
+                     "radix_passes": passes, "bytes_survey_model": int(bs),
+                     "frac_survey_model": round(bs / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "roofline": {"kernel": dom, "avg_launch_ms": round(avg, 5), "bytes_per_launch": int(bpl),
+                                  "achieved": round(bpl / (avg * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                                  "frac": round(bpl / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                     "kernels_ms": {x: round(v[1] / steps, 4) for x, v in sorted(k.items(), key=lambda kv: -kv[1][1])}}
+        del b, out, ws
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_batched(G, args) -> dict:
@@ -182,7 +241,20 @@ def run_batched(G, args) -> dict:
     same = same_as_plain(outs_b)
     same_g = g_status == G.GRID_OK and same_as_plain(outs_g)
     ntot = sum(caps)
+    cells_tot = sum(g.ncells for g in inputs)
+    plan = G.sort_plan(max(1, (cells_tot - 1).bit_length()))
+    b_survey = sum(survey_bytes(s.ntris, c, s.ncells, plan[0]) for s, c in zip(batch, caps))
+    sweeps = [(k, v) for k, v in kern.items() if k.startswith("onesweep")]
+    sw_launch, sw_ms = sum(v[0] for _, v in sweeps), sum(v[1] for _, v in sweeps)
+    batch_roof = None
+    if sw_launch:
+        avg = sw_ms / sw_launch
+        batch_roof = {"kernel": "onesweep (all passes)", "avg_launch_ms": round(avg, 5),
+                      "bytes_per_launch": 16 * int(ntot), "achieved": round(16 * ntot / (avg * 1e-3) / 1e9, 1),
+                      "peak": HBM_PEAK_GBS, "frac": round(16 * ntot / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     res = {"ngrids": len(inputs), "triangles": int(sum(s.ntris for s in batch)), "npairs": int(ntot),
+           "cells": int(cells_tot), "bytes_survey_model": int(b_survey),
+           "frac_survey_model": round(b_survey / tb / 1e9 / HBM_PEAK_GBS, 4), "roofline": batch_roof,
            "batched_builds_per_s": round(len(inputs) / tb, 1), "plain_builds_per_s": round(len(inputs) / tp, 1),
            "graph_builds_per_s": round(len(inputs) / tg, 1),
            "batched_ms": round(tb * 1e3, 3), "graph_ms": round(tg * 1e3, 3), "plain_ms": round(tp * 1e3, 3),
@@ -331,6 +403,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-grid batched build and serving")
     ap.add_argument("--no-serve", action="store_true", help="skip serving")
     ap.add_argument("--no-culled", action="store_true", help="skip the culled-build comparison")
+    ap.add_argument("--no-configs", action="store_true", help="skip the small and mixed single-grid configurations")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the per-object pair generation comparison")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
@@ -430,7 +503,11 @@ def main():
                     "events": "timed region" if dom in kern else "separate traced run"}
         b_alg = sum(kernel_bytes(k, T, NO, R) * v[0] for k, v in kern_all.items()) / args.steps
         kern_ms = sum(v[1] for v in kern_all.values()) / args.steps
+        passes = G.sort_plan(max(0, (R - 1).bit_length()))[0]
+        b_survey = survey_bytes(T, NO, R, passes)
         pipeline = {"bytes_alg_per_build": int(b_alg), "frac_of_peak_at_ms_per_build": round(b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "radix_passes": passes, "bytes_survey_model": int(b_survey),
+                    "frac_survey_model": round(b_survey / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                     "kernel_ms_per_build": round(kern_ms, 4),
                     "kernels": {k: {"launches_per_build": v[0] / args.steps, "avg_ms": round(v[1] / v[0], 5)}
                                 for k, v in sorted(kern_all.items(), key=lambda kv: -kv[1][1])}}
@@ -465,6 +542,9 @@ def main():
         "pipeline": pipeline,
         "cpu_baseline": None,
     }
+    if not args.no_configs:
+        print("# configurations", file=sys.stderr, flush=True)
+        result["configs"] = run_configs(G, args)
     if not args.no_batched:
         print("# batched", file=sys.stderr, flush=True)
         result["batched"], pool, pool_refs = run_batched(G, args)
