@@ -352,6 +352,89 @@ def run_culled(G, args, gin, out, ws, reps: int = 5) -> dict:
     return res
 
 
+def run_paths(G, args, gin, out, ws, reps: int = 5) -> dict:
+    """The sorted path against the compact path (atomic counting scatter plus
+    in-cell sorts) of grid_build on homogeneous and non-homogeneous scenes, and
+    the path the statistics pass picks (build_path = 2) with its time; every
+    path's grid is compared with the sorted path's on the device."""
+    import torch
+    from paper_2403_10647_amd import scenes
+    cases = [("small", None), ("uniform", 16_384), ("uniform", 65_536), ("uniform", 262_144), ("uniform", 1_000_000),
+             ("uniform", 4_000_000), ("mixed", None), ("hairball", None)]
+    res = {}
+    todo = [(args.workload, gin, out)]
+    for name, n in cases:
+        s = scenes.make_scene(name, seed=args.seed, ntris=n)
+        g = G.GridInput.from_scene(s)
+        no, _ = G.count(g, ws)
+        todo.append((f"{name}_{s.ntris}", g, G.build(g, cap_pairs=no, ws=ws)))
+    for label, g, ref in todo:
+        n = ref.npairs
+        row = {"triangles": g.ntris, "npairs": n, "cells": g.ncells, "pairs_per_cell": round(n / g.ncells, 3)}
+        o = G.build(g, cap_pairs=n, ws=ws)
+        for path, key in ((0, "sorted"), (1, "compact"), (2, "auto")):
+            G.tune_set("build_path", path)
+            try:
+                run = G.PlainBuild(g, o, ws)
+                run()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    run()
+                torch.cuda.synchronize()
+                row[f"{key}_ms"] = round((time.perf_counter() - t0) * 1e3 / reps, 4)
+                if path == 2:
+                    row["auto_path"] = ("sorted", "compact")[G.tune_get("last_path")]
+                if path == 1:  # where the compact path's time goes (a separate traced build)
+                    G.trace_enable(True)
+                    G.trace_read()
+                    run()
+                    row["compact_kernels_ms"] = {kk: round(v[1], 4) for kk, v in G.trace_read().items()}
+                    G.trace_enable(False)
+                row[f"{key}_identical"] = bool(torch.equal(o.cells[:n], ref.cells[:n]) and torch.equal(o.objs[:n], ref.objs[:n])
+                                               and torch.equal(o.ranges, ref.ranges))
+            finally:
+                G.tune_set("build_path", 0)
+        row["compact_over_sorted"] = round(row["compact_ms"] / row["sorted_ms"], 3)
+        res[label] = row
+        del o
+    return res
+
+
+def run_resolution(G, args, reps: int = 5) -> dict:
+    """The cell-size rule revisited (the paper leaves it open): the sorted build
+    of the 10M arch scene and the 1M mixed scene at lambda = 1, 2, 4, 8 cells
+    per triangle (the resolution rule's parameter), with the pair count, the
+    cells and the build time at each."""
+    import torch
+    from paper_2403_10647_amd import scenes
+    res = {}
+    for name, cap in (("arch", 1024), ("mixed", 512)):
+        s = scenes.make_scene(name, seed=args.seed)
+        base = G.GridInput.from_scene(s)
+        rows = {}
+        for lam in (1.0, 2.0, 4.0, 8.0):
+            r = scenes.resolution_rule(s.lo, s.hi, s.ntris, lam, cap)
+            g = G.GridInput(base.verts, base.tris, list(map(float, s.lo)), list(map(float, s.hi)), list(map(int, r)))
+            ws = G.Workspace()
+            n, _ = G.count(g, ws)
+            out = G.build(g, cap_pairs=n, ws=ws)
+            b = G.PlainBuild(g, out, ws)
+            b()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                b()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / reps
+            rows[f"lambda_{lam:g}"] = {"res": [int(x) for x in r], "cells": g.ncells, "npairs": n,
+                                       "pairs_per_triangle": round(n / s.ntris, 3), "ms_per_build": round(ms, 4)}
+            del b, out, ws, g
+        res[name] = rows
+        torch.cuda.empty_cache()
+    return res
+
+
 def run_served(G, args, pool, pool_refs, big, big_ref) -> dict:
     """Poisson arrivals of requests drawn from the batch's grids plus the 10M-triangle scene once a
     second, through the continuous-batching server; every output is compared on the device with the
@@ -404,6 +487,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip serving")
     ap.add_argument("--no-culled", action="store_true", help="skip the culled-build comparison")
     ap.add_argument("--no-configs", action="store_true", help="skip the small and mixed single-grid configurations")
+    ap.add_argument("--no-paths", action="store_true", help="skip the sorted/compact path comparison")
+    ap.add_argument("--no-resolution", action="store_true", help="skip the cell-size (lambda) sweep")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the per-object pair generation comparison")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
@@ -552,6 +637,12 @@ def main():
             print("# serving", file=sys.stderr, flush=True)
             result["served"] = run_served(G, args, pool, pool_refs, gin, out)
         del pool, pool_refs
+    if not args.no_paths:
+        print("# sorted and compact paths", file=sys.stderr, flush=True)
+        result["paths"] = run_paths(G, args, gin, out, ws)
+    if not args.no_resolution:
+        print("# resolution sweep", file=sys.stderr, flush=True)
+        result["resolution"] = run_resolution(G, args)
     if not args.no_culled:
         print("# culled builds", file=sys.stderr, flush=True)
         result["culled"] = run_culled(G, args, gin, out, ws)

@@ -243,6 +243,15 @@ int grid_scan_u32(const uint32_t *in, const uint32_t *flags, uint32_t *out, uint
  *                     one thread per pair (Section 3), equal work
  *                     whatever an object's size.  Ignored by batched builds and
  *                     while "fused_expand" is 1.
+ *   "build_path"      plain builds (grid_build, grid_build_static): 0 (default) the
+ *                     sorted path of Algorithm 1; 1 the compact path, the atomic
+ *                     construction the Related Work section compares against: per-cell
+ *                     counts with atomics, their exclusive scan into the range table,
+ *                     a counting scatter with atomics, then each cell's object ids
+ *                     sorted; 2 chosen per build after the count from its pair count
+ *                     and cell count (the statistics pass the Conclusions propose;
+ *                     one extra readback).  Culled and batched builds ignore it.
+ *   "last_path"       (read only) the path the last plain build took, 0 or 1.
  * Outputs never depend on the knobs.  GRID_E_INVAL for an unknown key or value. */
 int grid_tune_set(const char *key, int value);
 int grid_tune_get(const char *key, int *value);

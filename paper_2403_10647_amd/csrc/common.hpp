@@ -28,7 +28,7 @@ struct Control {
   uint64_t kept;               // culled builds: pairs that survive the overlap test
   uint64_t box_npairs;         // culled builds: the box pair count (npairs then holds the kept count)
   uint32_t tfo_work_n;         // tile-owner runs left for the plan kernel to write
-  uint32_t pad;
+  uint32_t big_n;              // compact builds: cells listed for the workgroup sort
 };
 constexpr uint32_t kErrBadIndex = 1u;
 constexpr uint32_t kErrInternal = 2u;  // an internal consistency check failed (the build's output is invalid)

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <vector>
 
+#include "compact.hpp"
 #include "cull.hpp"
 #include "kernels.hpp"
 #include "ranges.hpp"
@@ -33,6 +34,10 @@ constexpr int kMergeTile = kRangesBlock * kRangesK;
 constexpr int kScanBlock = 256, kScanK = 8;
 constexpr int kMakePairsBlock = 256;                    // per-object pair generation: one thread per object
 constexpr int kPlanBlock = 1024;
+constexpr int kCellScanBlock = 256, kCellScanK = 16;     // compact builds: 4096 cells per scan tile
+constexpr int kCellScanTile = kCellScanBlock * kCellScanK;
+constexpr uint64_t kCompactMaxPairs = uint64_t{1} << 18;  // build_path = 2: compact up to this many pairs ...
+constexpr double kCompactMaxPairsPerCell = 2.0;          // ... at or below this density
 constexpr int kMaxRadixBits = 11;
 constexpr int kKeyMapBits = 13;                         // batched key map: at most 8192 buckets
 static_assert((1 << kExpandTileShift) == kExpandTile, "expansion tile must be a power of two");
@@ -137,6 +142,11 @@ int g_fused_expand = 0;
 // one thread per object write all of that object's pairs (the sorted-grid
 // style the paper measures its per-pair expansion against), for comparison.
 int g_per_object_pairs = 0;
+// Plain builds: 0 = the sorted path (count, expansion, radix sort, ranges),
+// 1 = the compact path (counting scatter with atomics and in-cell sorts),
+// 2 = chosen per build from the count's statistics (one extra readback).
+int g_build_path = 0;
+int g_last_path = 0;  // the path the last plain build took
 int g_sort_shape = 3;  // radix passes from arrays: 0 = 512 x 16, 1 = 256 x 16, 2 = 1024 x 8, 3 = 1024 x 16,
                        // 4 = 1024 x 15
 
@@ -173,7 +183,7 @@ Plan make_plan(uint32_t bits, int max_digit = -1) {
 uint32_t tfo_work_cap(uint32_t ntfo) { return ntfo / kTfoInline + 2; }
 
 struct Layout {
-  size_t ctl, hist, count_status, cull_status, zero_end;
+  size_t ctl, hist, count_status, cull_status, cell_status, zero_end;
   size_t start, box, tfo, tfg, tfo_work, sort_status, keys_alt, vals_alt, keys_alt2, vals_alt2, run, npairs_out, splits,
       tile_grid, table, sink, kmap, ksink, total;
   uint32_t ntfo, ncount_tiles, nsort_tiles_cap, nmerge_tiles_cap;
@@ -196,6 +206,7 @@ Layout make_layout(uint64_t ntris, uint64_t cap_pairs, uint64_t ncells_plus_grid
   L.hist = take(static_cast<size_t>(kHistCopies) * 4 * kRadixMax * sizeof(uint32_t));
   L.count_status = take(std::max<size_t>(L.ncount_tiles, 1) * 8);
   L.cull_status = take(static_cast<size_t>(L.ntfo) * 8);  // culled builds: one word per expansion tile
+  L.cell_status = take(batched ? 0 : (ceil_div(ncells_plus_grids, kCellScanTile) + 1) * 8);  // compact builds
   L.zero_end = o;
   L.start = take(ntris * 4);
   L.box = take(ntris * 8);
@@ -270,6 +281,12 @@ int launch_zero(void* ws, size_t bytes, hipStream_t s) {
   zero_kernel<<<std::max(blocks, 1u), 256, 0, s>>>(static_cast<uint64_t*>(ws), words);
   GB_LAUNCHED();
   return GRID_OK;
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint64_t n, uint32_t v) {
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
 }
 
 struct Build {
@@ -427,6 +444,74 @@ int launch_expand(Build& b, uint32_t* cells, uint32_t* objs, uint64_t npairs) {
     GB_LAUNCHED();
   }
   return GRID_OK;
+}
+
+// The compact path of a plain build (after the count and the plan): counts
+// per cell, their scan into the range table, the counting scatter and the
+// in-cell sorts.  out->ranges serves as the per-cell counters throughout.
+int launch_compact(Build& b, const grid_out* out) {
+  CompactArgs a{};
+  a.ex = expand_args(b);
+  a.ranges = out->ranges;
+  a.cells = out->cells;
+  a.objs = out->objs;
+  a.cap = out->cap_pairs;
+  a.ncells = ncells_of(b.gs.one.res);
+  a.status = at<uint64_t>(b.ws, b.L.cell_status);
+  a.big = at<uint2>(b.ws, b.L.vals_alt);                       // the radix buffers are free on this path
+  a.big_cap = static_cast<uint32_t>(std::min<uint64_t>(out->cap_pairs / 2, 0xFFFFFFFFull));
+  a.scratch = at<uint32_t>(b.ws, b.L.keys_alt);
+  a.ctl = at<Control>(b.ws, b.L.ctl);
+  const uint64_t cap = out->cap_pairs;
+  {
+    TraceScope ts(b.s, "compact_zero");
+    const uint64_t n = 2 * a.ncells;
+    fill_u32_kernel<<<static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(n, 256), 4096))), 256, 0,
+                      b.s>>>(out->ranges, n, 0u);
+    GB_LAUNCHED();
+  }
+  if (cap > 0) {
+    TraceScope ts(b.s, "compact_count");
+    auto kern = compact_count_kernel<kExpandBlock, kExpandK>;
+    kern<<<resident_blocks(kern, kExpandBlock, ceil_div(cap, kExpandTile)), kExpandBlock, 0, b.s>>>(a);
+    GB_LAUNCHED();
+  }
+  {
+    TraceScope ts(b.s, "compact_scan");
+    auto kern = compact_scan_kernel<kCellScanBlock, kCellScanK>;
+    kern<<<resident_blocks(kern, kCellScanBlock, ceil_div(a.ncells, kCellScanTile)), kCellScanBlock, 0, b.s>>>(a);
+    GB_LAUNCHED();
+  }
+  if (cap > 0) {
+    {
+      TraceScope ts(b.s, "compact_scatter");
+      auto kern = compact_scatter_kernel<kExpandBlock, kExpandK>;
+      kern<<<resident_blocks(kern, kExpandBlock, ceil_div(cap, kExpandTile)), kExpandBlock, 0, b.s>>>(a);
+      GB_LAUNCHED();
+    }
+    {
+      TraceScope ts(b.s, "compact_sort_small");
+      compact_sort_small_kernel<256><<<static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(a.ncells, 256), 8192))),
+                                      256, 0, b.s>>>(a);
+      GB_LAUNCHED();
+    }
+    {
+      TraceScope ts(b.s, "compact_sort_big");
+      compact_sort_big_kernel<256><<<1024, 256, 0, b.s>>>(a);
+      GB_LAUNCHED();
+    }
+  }
+  return GRID_OK;
+}
+
+// The path a plain build takes when it is left to the statistics (knob
+// build_path = 2): the compact path's atomics cost more per pair than the
+// sorted path's passes, so it only pays where launches dominate, small sparse
+// grids (measured on MI355X: 0.78-0.90 of the sorted time up to 150K pairs,
+// 1.24 at 0.9M, 3.7-10 beyond).
+int choose_path(uint64_t npairs, uint64_t ncells) {
+  if (npairs == 0) return 0;
+  return npairs <= kCompactMaxPairs && static_cast<double>(npairs) <= kCompactMaxPairsPerCell * ncells ? 1 : 0;
 }
 
 // Culled builds: the expansion that tests every box pair and keeps the pairs
@@ -787,12 +872,23 @@ int grid_build(const float* verts_soa, uint32_t nverts, const uint32_t* tris, ui
   if ((st = launch_zero(b.ws, b.L.zero_end, b.s))) return st;
   if ((st = launch_count<false>(b))) return st;
   if ((st = launch_plan<false>(b))) return st;
-  if (b.plan.sp.passes == 0) {
+  int path = g_build_path;
+  if (path == 2) {
+    // the statistics pass: the count's totals, read back once, choose the path
+    Control c;
+    GB_TRY(hipMemcpyAsync(&c, at<Control>(b.ws, b.L.ctl), sizeof(Control), hipMemcpyDeviceToHost, b.s));
+    GB_TRY(hipStreamSynchronize(b.s));
+    path = choose_path(c.npairs, ncells_of(res));
+  }
+  g_last_path = path;
+  if (path == 1) {
+    if ((st = launch_compact(b, out))) return st;
+  } else if (b.plan.sp.passes == 0) {
     if ((st = launch_expand<0, false>(b, out->cells, out->objs, cap))) return st;
   } else if (cap > 0) {
     if ((st = launch_sort<false>(b, out->cells, out->objs, cap))) return st;
   }
-  if ((st = launch_ranges<false>(b, ncells_of(res) + 1 + cap))) return st;
+  if (path != 1 && (st = launch_ranges<false>(b, ncells_of(res) + 1 + cap))) return st;
   HostCtl h{};
   if ((st = read_ctl(b, &h))) return st;
   out->npairs = h.npairs;
@@ -1310,6 +1406,11 @@ int grid_tune_set(const char* key, int value) {
     g_per_object_pairs = value;
     return GRID_OK;
   }
+  if (std::strcmp(key, "build_path") == 0) {
+    if (value < 0 || value > 2) return GRID_E_INVAL;
+    g_build_path = value;
+    return GRID_OK;
+  }
   return GRID_E_INVAL;
 }
 
@@ -1329,6 +1430,8 @@ int grid_tune_get(const char* key, int* value) {
   if (std::strcmp(key, "fused_expand") == 0) { *value = g_fused_expand; return GRID_OK; }
   if (std::strcmp(key, "sort_shape") == 0) { *value = g_sort_shape; return GRID_OK; }
   if (std::strcmp(key, "per_object_pairs") == 0) { *value = g_per_object_pairs; return GRID_OK; }
+  if (std::strcmp(key, "build_path") == 0) { *value = g_build_path; return GRID_OK; }
+  if (std::strcmp(key, "last_path") == 0) { *value = g_last_path; return GRID_OK; }
   return GRID_E_INVAL;
 }
 

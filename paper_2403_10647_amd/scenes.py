@@ -13,6 +13,8 @@ none of them are available here, so these generators stand in for them:
   the size class of the paper's 10M-triangle real-time claim (abstract).
 * ``batch``  - 512 independent ``mixed``-style grids with log-uniform
   triangle counts in [1e3, 2e5].
+* ``uniform`` - ``mixed`` without its large triangles: small triangles spread
+  evenly, the homogeneous case (about four cells per triangle).
 * ``hairball`` - long, thin, diagonal slivers (strands of random direction,
   lengths log-uniform in [0.3, 3], widths near 1% of the length) in a
   [0, 10]^3 box: the shape of the paper's Hairball scene, whose triangles'
@@ -37,8 +39,8 @@ __all__ = [
     "resolution_rule", "aabb_bounds", "SCENE_NAMES",
 ]
 
-SCENE_NAMES = ("small", "mixed", "arch", "batch", "hairball")
-_STREAM = {"small": 0, "mixed": 1, "arch": 2, "batch": 3, "serve": 4, "hairball": 5}
+SCENE_NAMES = ("small", "mixed", "arch", "batch", "hairball", "uniform")
+_STREAM = {"small": 0, "mixed": 1, "arch": 2, "batch": 3, "serve": 4, "hairball": 5, "uniform": 6}
 
 
 @dataclasses.dataclass
@@ -225,6 +227,14 @@ def _hairball_scene(seed: int, ntris: int = 1_000_000, lam: float = 4.0, cap: in
     return Scene("hairball", verts, tris, lo, hi, resolution_rule(lo, hi, ntris, lam, cap), seed)
 
 
+def _uniform_scene(seed: int, ntris: int = 1_000_000, lam: float = 4.0, cap: int = 512) -> Scene:
+    rng = _rng(seed, _STREAM["uniform"])
+    v = rng.uniform(0.0, 10.0, size=(ntris, 1, 3)) + rng.uniform(-0.05, 0.05, size=(ntris, 3, 3))
+    verts, tris = soup_from_vertices(v)
+    lo, hi = aabb_bounds(verts)
+    return Scene("uniform", verts, tris, lo, hi, resolution_rule(lo, hi, ntris, lam, cap), seed)
+
+
 def make_scene(name: str, seed: int = 0, ntris: Optional[int] = None) -> Scene:
     """Build one of the named single-grid scenes (``ntris`` rescales it for tests)."""
     if name == "small":
@@ -238,4 +248,6 @@ def make_scene(name: str, seed: int = 0, ntris: Optional[int] = None) -> Scene:
         return _arch_scene(seed, ntris, nwalls=nwalls, nclusters=max(1, ntris // 5000))
     if name == "hairball":
         return _hairball_scene(seed, ntris or 1_000_000)
-    raise ValueError(f"unknown scene {name!r}; expected one of small, mixed, arch, hairball")
+    if name == "uniform":
+        return _uniform_scene(seed, ntris or 1_000_000)
+    raise ValueError(f"unknown scene {name!r}; expected one of small, mixed, arch, hairball, uniform")
