@@ -68,6 +68,7 @@ def lib():
         L.oracle_make_pairs_culled.restype = C.c_uint64
         L.oracle_build_culled.argtypes = [P, C.c_uint32, P, C.c_uint32, P, P, P, P, P, P, C.c_uint64, P, P]
         L.oracle_build_culled.restype = C.c_int
+        L.oracle_raycast.argtypes = [P, C.c_uint32, P, C.c_uint32, P, P, P, C.c_uint32, C.c_float, P, P]
         _lib = L
     return _lib
 
@@ -277,3 +278,19 @@ def build_culled(verts, tris, lo, hi, res):
 
 def build_scene_culled(scene):
     return build_culled(scene.verts, scene.tris, scene.lo, scene.hi, scene.res)
+
+
+def raycast(verts, tris, lo, hi, rays, tmax: float = float("inf")):
+    """Closest hits by brute force over every triangle (rays: float32 [6, N],
+    origins then directions): (hit t float32 [N], hit object uint32 [N])."""
+    verts = np.ascontiguousarray(verts, np.float32)
+    tris = np.ascontiguousarray(tris, np.uint32)
+    lo = np.ascontiguousarray(lo, np.float32)
+    hi = np.ascontiguousarray(hi, np.float32)
+    rays = np.ascontiguousarray(rays, np.float32)
+    n = rays.shape[1]
+    ht = np.zeros(n, np.float32)
+    ho = np.zeros(n, np.uint32)
+    lib().oracle_raycast(_p(verts), verts.shape[1], _p(tris), tris.shape[0], _p(lo), _p(hi), _p(rays), n,
+                         C.c_float(tmax), _p(ht), _p(ho))
+    return ht, ho

@@ -350,3 +350,112 @@ int oracle_build_culled(const float* verts_soa, uint32_t nverts, const uint32_t*
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Ray casting, the use the grid is built for (Introduction; Related Work: the
+// grid answers ray and spatial queries): the closest triangle a ray hits,
+// here by brute force over every triangle, which is the plain definition the
+// grid traversal must reproduce.  Readings (the paper gives no query):
+//  * a ray is o + t d for t in [t0, t1], where [t0, t1] clips [0, tmax] to
+//    the grid box [lo, hi] by the slab test (per axis with d != 0:
+//    t = (lo - o) / d and (hi - o) / d; an axis with d = 0 and o outside
+//    [lo, hi] leaves no interval); only hits inside the box count, the part
+//    of space the grid covers;
+//  * the hit test is Moller and Trumbore's, every operation one FP32 operation
+//    in the order written (no contraction, IEEE division); a triangle whose
+//    plane the ray meets at a grazing angle (det^2 < 1e-8 |e1|^2 |e2|^2 |d|^2,
+//    an angle below about 1e-4 rad) or that is degenerate is missed; edges
+//    and vertices count as hits;
+//  * the result is the smallest hit t and, among triangles hit at exactly that
+//    t, the smallest id; no hit gives t = +inf and id 0xFFFFFFFF.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr float kGrazing = 1e-8f;
+
+inline void cross3(const float a[3], const float b[3], float r[3]) {
+  r[0] = a[1] * b[2] - a[2] * b[1];
+  r[1] = a[2] * b[0] - a[0] * b[2];
+  r[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// The hit parameter of ray (o, d) with triangle (v0, v1, v2), or +inf.
+float ray_triangle(const float o[3], const float d[3], const float v0[3], const float v1[3], const float v2[3]) {
+  float e1[3], e2[3], s[3], p[3], q[3];
+  for (int a = 0; a < 3; ++a) {
+    e1[a] = v1[a] - v0[a];
+    e2[a] = v2[a] - v0[a];
+    s[a] = o[a] - v0[a];
+  }
+  cross3(d, e2, p);
+  float det = dot3(e1, p);
+  const float lim = ((dot3(e1, e1) * dot3(e2, e2)) * dot3(d, d)) * kGrazing;
+  if (!(det * det >= lim) || det == 0.0f) return INFINITY;
+  float u = dot3(s, p);
+  cross3(s, e1, q);
+  float v = dot3(d, q);
+  float tn = dot3(e2, q);
+  if (det < 0.0f) {
+    det = -det;
+    u = -u;
+    v = -v;
+    tn = -tn;
+  }
+  if (!(u >= 0.0f && v >= 0.0f && u + v <= det)) return INFINITY;
+  return tn / det;
+}
+
+// [t0, t1]: [0, tmax] clipped to the box; false when empty.
+bool clip_to_box(const float o[3], const float d[3], const float lo[3], const float hi[3], float tmax, float* t0,
+                 float* t1) {
+  float a0 = 0.0f, a1 = tmax;
+  for (int a = 0; a < 3; ++a) {
+    if (d[a] != 0.0f) {
+      const float ta = (lo[a] - o[a]) / d[a];
+      const float tb = (hi[a] - o[a]) / d[a];
+      a0 = std::fmax(a0, std::fmin(ta, tb));
+      a1 = std::fmin(a1, std::fmax(ta, tb));
+    } else if (!(o[a] >= lo[a] && o[a] <= hi[a])) {
+      return false;
+    }
+  }
+  *t0 = a0;
+  *t1 = a1;
+  return a0 <= a1;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Closest hits of nrays rays (rays: FP32 [6][nrays], origin x, y, z then
+// direction x, y, z) with the triangles, within the grid box and tmax.
+void oracle_raycast(const float* verts_soa, uint32_t nverts, const uint32_t* tris, uint32_t ntris, const float lo[3],
+                    const float hi[3], const float* rays, uint32_t nrays, float tmax, float* hit_t, uint32_t* hit_obj) {
+  for (uint32_t r = 0; r < nrays; ++r) {
+    float o[3], d[3];
+    for (int a = 0; a < 3; ++a) {
+      o[a] = rays[static_cast<size_t>(a) * nrays + r];
+      d[a] = rays[static_cast<size_t>(3 + a) * nrays + r];
+    }
+    float best = INFINITY, t0 = 0.0f, t1 = 0.0f;
+    uint32_t id = 0xFFFFFFFFu;
+    if (clip_to_box(o, d, lo, hi, tmax, &t0, &t1)) {
+      for (uint32_t t = 0; t < ntris; ++t) {
+        float v[3][3];
+        for (int j = 0; j < 3; ++j)
+          for (int a = 0; a < 3; ++a) v[j][a] = verts_soa[static_cast<size_t>(a) * nverts + tris[3 * static_cast<size_t>(t) + j]];
+        const float th = ray_triangle(o, d, v[0], v[1], v[2]);
+        if (th >= t0 && th <= t1 && th < best) {
+          best = th;
+          id = t;
+        }
+      }
+    }
+    hit_t[r] = best;
+    hit_obj[r] = id;
+  }
+}
+
+}  // extern "C"

@@ -49,6 +49,12 @@ MUTATIONS = {
     "cull_no_normal_axis": ("  if (axis_separates(n, u, b)) return false;\n", ""),
     "cull_margin_shrinks": ("const float above = (tmax + mg) - lo_off;", "const float above = (tmax - mg) - lo_off;"),
     "cull_box_offset_swapped": ("const float below = (tmin - mg) - hi_off;", "const float below = (tmin - mg) - lo_off;"),
+    # ray casting
+    "ray_det_sign_ignored": ("  if (det < 0.0f) {\n    det = -det;\n    u = -u;\n    v = -v;\n    tn = -tn;\n  }\n", ""),
+    "ray_q_cross_swapped": ("cross3(s, e1, q);", "cross3(e1, s, q);"),
+    "ray_clip_ignores_box": ("  *t0 = a0;\n  *t1 = a1;\n  return a0 <= a1;", "  *t0 = 0.0f;\n  *t1 = tmax;\n  return true;"),
+    "ray_tie_keeps_last": ("th >= t0 && th <= t1 && th < best", "th >= t0 && th <= t1 && th <= best"),
+    "ray_t_from_u": ("return tn / det;", "return u / det;"),
 }
 
 
@@ -71,6 +77,7 @@ def _compile(tmp_path, name, src):
     L.oracle_count_cells.restype = C.c_int
     L.oracle_make_pairs_culled.argtypes = [P, C.c_uint32, P, C.c_uint32, P, P, P, P, P, P, P, P, P]
     L.oracle_make_pairs_culled.restype = C.c_uint64
+    L.oracle_raycast.argtypes = [P, C.c_uint32, P, C.c_uint32, P, P, P, C.c_uint32, C.c_float, P, P]
     return L
 
 
@@ -189,9 +196,24 @@ def _cull_pass(L) -> bool:
     return True
 
 
+def _raycast_pass(L) -> bool:
+    import raycast_pins
+
+    def fn(verts, tris, lo, hi, rays, tmax):
+        verts, tris = np.ascontiguousarray(verts, np.float32), np.ascontiguousarray(tris, np.uint32)
+        lo, hi = np.ascontiguousarray(lo, np.float32), np.ascontiguousarray(hi, np.float32)
+        rays = np.ascontiguousarray(rays, np.float32)
+        n = rays.shape[1]
+        ht, ho = np.zeros(n, np.float32), np.zeros(n, np.uint32)
+        L.oracle_raycast(_p(verts), verts.shape[1], _p(tris), tris.shape[0], _p(lo), _p(hi), _p(rays), n,
+                         C.c_float(tmax), _p(ht), _p(ho))
+        return ht, ho
+    return raycast_pins.check(fn)
+
+
 def _pins_pass(L) -> bool:
-    """Run the brute-force, GlobalCoords, FP32 cell-face and culling pins against library L."""
-    if not _faces_pass(L) or not _cull_pass(L):
+    """Run the brute-force, GlobalCoords, FP32 cell-face, culling and ray-casting pins against library L."""
+    if not _faces_pass(L) or not _cull_pass(L) or not _raycast_pass(L):
         return False
     lo5 = np.array([5, 7, 11], np.uint32)
     for m in [(2, 3, 4), (3, 1, 2), (4, 4, 1)]:
