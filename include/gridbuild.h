@@ -199,6 +199,29 @@ int grid_workspace_status(const void *ws, uint64_t *npairs_total, void *stream);
 int grid_build_static(const float *verts_soa, uint32_t nverts, const uint32_t *tris, uint32_t ntris,
                       const float lo[3], const float hi[3], const uint32_t res[3], grid_out *out, void *stream);
 
+/* ---- using the grid ---------------------------------------------------------- */
+
+/* Ray casting over a built grid, the query the grid exists to speed up
+ * (Introduction; Related Work): for each ray, the closest triangle it hits.
+ * The grid is (ranges, objs) of a build of these triangles with these lo, hi,
+ * res (device arrays as grid_build wrote them; objs holds NO entries).
+ * rays: device FP32 [6][nrays], origin x, y, z then direction x, y, z (any
+ * length).  A ray is o + t d for t in [t0, t1], [0, tmax] clipped to the grid
+ * box [lo, hi] by the slab test (per axis with d != 0, t = (lo - o) / d and
+ * (hi - o) / d; an axis with d = 0 and o outside the box leaves nothing): only
+ * hits inside the box count.  The hit test is Moller and Trumbore's in a fixed
+ * order of FP32 operations (no contraction, IEEE division); a ray at a grazing
+ * angle to a triangle (det^2 < 1e-8 |e1|^2 |e2|^2 |d|^2) or a degenerate
+ * triangle misses; edges count.  Outputs (device): hit_t[r] = the smallest hit
+ * t (+inf if none), hit_obj[r] = its triangle, the smallest id among equal t
+ * (0xFFFFFFFF if none): exactly what testing every triangle gives.  Object ids
+ * or vertex indices out of range never hit.  Does not synchronize the stream.
+ * GRID_E_INVAL for a bad grid, null pointers, or tmax < 0 or NaN. */
+int grid_raycast(const float *verts_soa, uint32_t nverts, const uint32_t *tris, uint32_t ntris,
+                 const float lo[3], const float hi[3], const uint32_t res[3],
+                 const uint32_t *ranges, const uint32_t *objs, const float *rays, uint32_t nrays,
+                 float tmax, float *hit_t, uint32_t *hit_obj, void *stream);
+
 /* ---- building blocks, exposed for testing and reuse ------------------------ */
 
 /* Stable LSD radix sort of (keys, vals) by the low nbits bits of keys

@@ -37,6 +37,7 @@ EXPORTS = (
     "grid_sort_workspace_size", "grid_sort_pairs", "grid_scan_workspace_size", "grid_scan_u32",
     "grid_trace_enable", "grid_trace_read", "grid_tune_set", "grid_tune_get", "grid_sort_plan",
     "grid_batch_staging_size", "grid_build_batched_async", "grid_workspace_status", "grid_trace_only",
+    "grid_raycast",
 )
 
 STATIC_SCRATCH_BYTES = 64 << 20   # GRID_STATIC_SCRATCH_BYTES: the static workspace of grid_build_static
@@ -112,6 +113,8 @@ def lib():
         L.grid_sort_plan.argtypes = [U32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
         L.grid_sort_plan.restype = C.c_int
         L.grid_tune_get.restype = C.c_int
+        L.grid_raycast.argtypes = [P, U32, P, U32, F3, F3, U3, P, P, P, U32, C.c_float, P, P, P]
+        L.grid_raycast.restype = C.c_int
         L.grid_trace_enable.argtypes = [C.c_int]
         L.grid_trace_only.argtypes = [C.c_char_p]
         L.grid_trace_only.restype = C.c_int
@@ -492,6 +495,20 @@ def scan_u32(x: torch.Tensor, op: int, flags: Optional[torch.Tensor] = None, ws:
                          C.c_void_p(out.data_ptr()), n, op, wp, wn, C.byref(tot), _stream(stream))
     _check(st, "grid_scan_u32")
     return out, int(tot.value)
+
+
+def raycast(g: GridInput, grid: GridResult, rays: torch.Tensor, tmax: float = float("inf"), stream=None):
+    """Closest hits of rays (float32 [6, N] on the device: origins, then directions)
+    over a built grid of g: (hit t float32 [N], hit object int32 [N], 0xFFFFFFFF if none)."""
+    assert rays.dtype == torch.float32 and rays.is_contiguous() and rays.dim() == 2 and rays.shape[0] == 6
+    n = int(rays.shape[1])
+    ht = torch.empty(max(n, 1), dtype=torch.float32, device=rays.device)
+    ho = torch.empty(max(n, 1), dtype=torch.int32, device=rays.device)
+    st = lib().grid_raycast(*_input_args(g), C.c_void_p(grid.ranges.data_ptr()), C.c_void_p(grid.objs.data_ptr()),
+                            C.c_void_p(rays.data_ptr()), n, C.c_float(tmax), C.c_void_p(ht.data_ptr()),
+                            C.c_void_p(ho.data_ptr()), _stream(stream))
+    _check(st, "grid_raycast")
+    return ht[:n], ho[:n]
 
 
 def trace_enable(on: bool = True):

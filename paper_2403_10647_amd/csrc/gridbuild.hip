@@ -12,6 +12,7 @@
 
 #include "compact.hpp"
 #include "cull.hpp"
+#include "raycast.hpp"
 #include "kernels.hpp"
 #include "ranges.hpp"
 #include "scan.hpp"
@@ -1474,6 +1475,38 @@ int grid_workspace_status(const void* ws, uint64_t* npairs_total, void* stream) 
   if (c.error) return device_error(c.error);
   if (c.cap_flag & 2u) return GRID_E_OVERFLOW;
   if (c.cap_flag & 1u) return GRID_E_CAPACITY;
+  return GRID_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// Ray casting over a built grid.
+// ---------------------------------------------------------------------------------
+extern "C" {
+
+int grid_raycast(const float* verts_soa, uint32_t nverts, const uint32_t* tris, uint32_t ntris, const float lo[3],
+                 const float hi[3], const uint32_t res[3], const uint32_t* ranges, const uint32_t* objs,
+                 const float* rays, uint32_t nrays, float tmax, float* hit_t, uint32_t* hit_obj, void* stream) {
+  int st = check_grid(lo, hi, res);
+  if (st) return st;
+  if (nrays == 0) return GRID_OK;
+  if (!rays || !hit_t || !hit_obj || !ranges || (ntris > 0 && (!verts_soa || !tris))) return GRID_E_INVAL;
+  if (!(tmax >= 0.0f)) return GRID_E_INVAL;
+  RaycastArgs a{};
+  a.g = make_grid(verts_soa, nverts, tris, ntris, lo, hi, res);
+  for (int k = 0; k < 3; ++k) a.hi[k] = hi[k];
+  a.ranges = ranges;
+  a.objs = objs;
+  a.rays = rays;
+  a.nrays = nrays;
+  a.tmax = tmax;
+  a.hit_t = hit_t;
+  a.hit_obj = hit_obj;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  TraceScope ts(s, "raycast");
+  raycast_kernel<256><<<static_cast<uint32_t>(ceil_div(nrays, 256)), 256, 0, s>>>(a);
+  GB_LAUNCHED();
   return GRID_OK;
 }
 

@@ -36,11 +36,11 @@ import numpy as np
 
 __all__ = [
     "Scene", "make_scene", "make_batch", "batch_sizes", "soup_from_vertices",
-    "resolution_rule", "aabb_bounds", "SCENE_NAMES",
+    "resolution_rule", "aabb_bounds", "SCENE_NAMES", "make_rays",
 ]
 
 SCENE_NAMES = ("small", "mixed", "arch", "batch", "hairball", "uniform")
-_STREAM = {"small": 0, "mixed": 1, "arch": 2, "batch": 3, "serve": 4, "hairball": 5, "uniform": 6}
+_STREAM = {"small": 0, "mixed": 1, "arch": 2, "batch": 3, "serve": 4, "hairball": 5, "uniform": 6, "rays": 7}
 
 
 @dataclasses.dataclass
@@ -251,3 +251,24 @@ def make_scene(name: str, seed: int = 0, ntris: Optional[int] = None) -> Scene:
     if name == "uniform":
         return _uniform_scene(seed, ntris or 1_000_000)
     raise ValueError(f"unknown scene {name!r}; expected one of small, mixed, arch, hairball, uniform")
+
+
+def make_rays(scene: Scene, n: int, seed: int = 0, outside: float = 0.3) -> np.ndarray:
+    """Seeded rays for queries over a scene's grid, float32 [6, n] (origins x, y,
+    z, then directions x, y, z): a share ``outside`` starts outside the grid box
+    (one box extent away) and aims at a uniform point inside it; the rest start
+    uniformly inside the box with directions uniform on the sphere."""
+    rng = _rng(seed, _STREAM["rays"])
+    lo = scene.lo.astype(np.float64)
+    hi = scene.hi.astype(np.float64)
+    ext = hi - lo
+    n_out = int(round(n * outside))
+    n_in = n - n_out
+    o_in = lo + rng.uniform(0.0, 1.0, size=(n_in, 3)) * ext
+    d_in = _unit_sphere(rng, (n_in,))
+    target = lo + rng.uniform(0.0, 1.0, size=(n_out, 3)) * ext
+    o_out = (lo + hi) / 2 + _unit_sphere(rng, (n_out,)) * np.linalg.norm(ext)
+    d_out = target - o_out
+    o = np.concatenate([o_in, o_out])
+    d = np.concatenate([d_in, d_out])
+    return np.ascontiguousarray(np.concatenate([o.T, d.T]), np.float32)

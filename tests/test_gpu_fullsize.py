@@ -89,3 +89,16 @@ def test_culled_full(G, name):
     _say(name, s.ntris, list(s.res))
     nbox, kept = _full_culled(G, s)
     assert 0 < kept < nbox
+
+
+def test_raycast_arch_full_sampled(G):
+    # the 10M-triangle grid, rays checked one by one against the brute force
+    s = scenes.make_scene("arch", seed=0)
+    g = G.GridInput.from_scene(s)
+    r = G.build(g)
+    rays = scenes.make_rays(s, 24, seed=5)
+    ht, ho = G.raycast(g, r, torch.from_numpy(rays).cuda())
+    ot, oo = oracle.raycast(s.verts, s.tris, s.lo, s.hi, rays)
+    assert np.array_equal(ho.cpu().numpy().view(np.uint32), oo)
+    assert np.array_equal(ht.cpu().numpy().view(np.uint32), ot.view(np.uint32))
+    assert (oo != 0xFFFFFFFF).sum() >= 12
