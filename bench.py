@@ -401,17 +401,54 @@ def run_paths(G, args, gin, out, ws, reps: int = 5) -> dict:
     return res
 
 
+def time_raycast(G, g, grid, rays, reps: int = 3):
+    """ms for one grid_raycast of the rays over the grid (event-timed, after a warm-up) and the hit count."""
+    import torch
+    ht, ho = G.raycast(g, grid, rays)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        G.raycast(g, grid, rays)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, int((ho != -1).sum().item())
+
+
+def run_raycast(G, args, scene, gin, out, ws, nrays: int = 1 << 20) -> dict:
+    """Closest-hit ray casting over the headline grid (the query the grid is
+    built for): 1M seeded rays (70% starting inside the box in uniform
+    directions, 30% aimed in from outside), over the sorted grid and over the
+    culled grid of the same scene, with the outputs of the two compared."""
+    import torch
+    from paper_2403_10647_amd import scenes
+    rays = torch.from_numpy(scenes.make_rays(scene, nrays, seed=args.seed)).cuda()
+    ms, hits = time_raycast(G, gin, out, rays)
+    ht, ho = G.raycast(gin, out, rays)
+    nbox = out.npairs
+    culled, _ = G.build_culled(gin, box_cap=nbox, ws=ws)
+    ms_c, _ = time_raycast(G, gin, culled, rays)
+    ct, co = G.raycast(gin, culled, rays)
+    same = bool(torch.equal(ht.view(torch.int32), ct.view(torch.int32)) and torch.equal(ho, co))
+    del culled
+    return {"rays": nrays, "hits": hits, "ms": round(ms, 4), "Mrays_per_s": round(nrays / (ms * 1e-3) / 1e6, 1),
+            "culled_grid_ms": round(ms_c, 4), "culled_grid_Mrays_per_s": round(nrays / (ms_c * 1e-3) / 1e6, 1),
+            "culled_grid_identical_hits": same}
+
+
 def run_resolution(G, args, reps: int = 5) -> dict:
     """The cell-size rule revisited (the paper leaves it open): the sorted build
     of the 10M arch scene and the 1M mixed scene at lambda = 1, 2, 4, 8 cells
     per triangle (the resolution rule's parameter), with the pair count, the
-    cells and the build time at each."""
+    cells, the build time and the time to cast 256K seeded rays over the grid
+    (scaled to 1M rays) at each: finer cells cost build time and save query time."""
     import torch
     from paper_2403_10647_amd import scenes
     res = {}
     for name, cap in (("arch", 1024), ("mixed", 512)):
         s = scenes.make_scene(name, seed=args.seed)
         base = G.GridInput.from_scene(s)
+        rays = torch.from_numpy(scenes.make_rays(s, 1 << 18, seed=args.seed)).cuda()
         rows = {}
         for lam in (1.0, 2.0, 4.0, 8.0):
             r = scenes.resolution_rule(s.lo, s.hi, s.ntris, lam, cap)
@@ -427,8 +464,11 @@ def run_resolution(G, args, reps: int = 5) -> dict:
                 b()
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3 / reps
+            rms, hits = time_raycast(G, g, out, rays)
             rows[f"lambda_{lam:g}"] = {"res": [int(x) for x in r], "cells": g.ncells, "npairs": n,
-                                       "pairs_per_triangle": round(n / s.ntris, 3), "ms_per_build": round(ms, 4)}
+                                       "pairs_per_triangle": round(n / s.ntris, 3), "ms_per_build": round(ms, 4),
+                                       "raycast_ms_per_1M_rays": round(rms * (1 << 20) / rays.shape[1], 4),
+                                       "hits": hits}
             del b, out, ws, g
         res[name] = rows
         torch.cuda.empty_cache()
@@ -489,6 +529,7 @@ def main():
     ap.add_argument("--no-configs", action="store_true", help="skip the small and mixed single-grid configurations")
     ap.add_argument("--no-paths", action="store_true", help="skip the sorted/compact path comparison")
     ap.add_argument("--no-resolution", action="store_true", help="skip the cell-size (lambda) sweep")
+    ap.add_argument("--no-raycast", action="store_true", help="skip ray casting over the headline grid")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the per-object pair generation comparison")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
@@ -640,6 +681,9 @@ def main():
     if not args.no_paths:
         print("# sorted and compact paths", file=sys.stderr, flush=True)
         result["paths"] = run_paths(G, args, gin, out, ws)
+    if not args.no_raycast:
+        print("# ray casting", file=sys.stderr, flush=True)
+        result["raycast"] = run_raycast(G, args, scene, gin, out, ws)
     if not args.no_resolution:
         print("# resolution sweep", file=sys.stderr, flush=True)
         result["resolution"] = run_resolution(G, args)
