@@ -493,6 +493,8 @@ def run_served(G, args, pool, pool_refs, big, big_ref) -> dict:
                                big_every=1.0, big_key=big_key)
     print(f"# serving {len(reqs)} requests over {args.serve_seconds} s", file=sys.stderr, flush=True)
     st = srv.run(reqs).as_dict()
+    # requests one at a time: one every millisecond, each done long before the next arrives
+    lone = srv.run(serve.spaced_requests(pool, gap=1e-3, count=1000, seed=args.seed + 2)).as_dict()
     burst = serve.make_requests(pool, rate=2000.0, duration=1.0, seed=args.seed + 1, big=big, big_key=big_key,
                                 burst=True)
     srv.run(burst)                      # untimed: sizes the allocator's blocks for batches this large
@@ -507,8 +509,10 @@ def run_served(G, args, pool, pool_refs, big, big_ref) -> dict:
     del srv_t
     torch.cuda.empty_cache()
     plain = serve.plain_builds_per_s(burst)
-    ok = st["mismatches"] == 0 and sb["mismatches"] == 0 and stt["mismatches"] == 0
+    ok = st["mismatches"] == 0 and sb["mismatches"] == 0 and stt["mismatches"] == 0 and lone["mismatches"] == 0
     return {"open_loop": {"rate_per_s": args.serve_rate, "big_every_s": 1.0, **st},
+            "lone": {"gap_ms": 1.0, **{k: lone[k] for k in ("requests", "completed", "p50_ms", "p99_ms",
+                                                                    "max_ms", "mean_batch", "mismatches")}},
             "burst": sb, "burst_tight_budget": stt,
             "burst_plain_builds_per_s": round(plain["builds_per_s"], 1),
             "burst_speedup_vs_plain": round(sb["builds_per_s"] / plain["builds_per_s"], 3),

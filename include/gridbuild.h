@@ -181,6 +181,39 @@ int grid_build_batched_async(const grid_desc *grids, uint32_t ngrids, void *ws, 
  * pair count.  Synchronizes stream. */
 int grid_workspace_status(const void *ws, uint64_t *npairs_total, void *stream);
 
+/* A batched build split in two halves around its count, so that a server can
+ * size the outputs from the exact NO (Algorithm 1: CountCells and
+ * ExclusiveSum give NO before any pair exists) without counting twice and
+ * without a host wait inside either call.
+ *
+ * grid_count_batched_async enqueues the count of the batch into ws: its
+ * triangle starts, cell boxes, tile owners and per-grid pair runs stay there
+ * for the second half.  Output pointers are not read.  The workspace layout
+ * holds as many pairs as ws_bytes allows; *pair_cap (host, if not NULL)
+ * receives that number at once.  When the stream has passed the call,
+ * counts_host[g] (host memory of ngrids + 1 words, pinned for the copy to stay
+ * asynchronous) holds grid g's NO and counts_host[ngrids] a status word:
+ * bit 0 a bad vertex index, bit 1 an internal check failed, bit 2 the pairs
+ * exceed *pair_cap, bit 3 they exceed 2^32 - 1.  A nonzero status means the
+ * batch cannot be resumed (a resumed build would write nothing).
+ * host_staging: caller-owned pinned memory of at least
+ * 2 * grid_batch_staging_size(ngrids) bytes; its first half keeps the counted
+ * table until the second half has been enqueued.
+ *
+ * grid_build_batched_counted enqueues the rest of that build: the radix
+ * passes and the ranges into the grids' outputs.  grids: the same grids in the
+ * same order (GRID_E_INVAL otherwise, checked on the host before anything is
+ * enqueued), now with outputs whose cap_pairs hold at least each grid's NO;
+ * ws, ws_bytes, host_staging and stream as in the count, with no other build on
+ * ws in between and the tuning knobs unchanged.  A grid above its capacity
+ * stops every kernel before it writes and is reported by grid_workspace_status.
+ * Outputs are identical to grid_build's for each grid. */
+int grid_count_batched_async(const grid_desc *grids, uint32_t ngrids, void *ws, size_t ws_bytes,
+                             void *host_staging, size_t staging_bytes, uint64_t *counts_host,
+                             uint64_t *pair_cap, void *stream);
+int grid_build_batched_counted(const grid_desc *grids, uint32_t ngrids, void *ws, size_t ws_bytes,
+                               void *host_staging, size_t staging_bytes, void *stream);
+
 /* ---- a build that allocates nothing ----------------------------------------- */
 
 /* For callers that cannot allocate device memory or take a workspace argument

@@ -37,7 +37,7 @@ EXPORTS = (
     "grid_sort_workspace_size", "grid_sort_pairs", "grid_scan_workspace_size", "grid_scan_u32",
     "grid_trace_enable", "grid_trace_read", "grid_tune_set", "grid_tune_get", "grid_sort_plan",
     "grid_batch_staging_size", "grid_build_batched_async", "grid_workspace_status", "grid_trace_only",
-    "grid_raycast",
+    "grid_raycast", "grid_count_batched_async", "grid_build_batched_counted",
 )
 
 STATIC_SCRATCH_BYTES = 64 << 20   # GRID_STATIC_SCRATCH_BYTES: the static workspace of grid_build_static
@@ -105,6 +105,10 @@ def lib():
         L.grid_batch_staging_size.restype = SZ
         L.grid_build_batched_async.argtypes = [C.POINTER(grid_desc), U32, P, SZ, P, SZ, P]
         L.grid_build_batched_async.restype = C.c_int
+        L.grid_count_batched_async.argtypes = [C.POINTER(grid_desc), U32, P, SZ, P, SZ, P, C.POINTER(C.c_uint64), P]
+        L.grid_count_batched_async.restype = C.c_int
+        L.grid_build_batched_counted.argtypes = [C.POINTER(grid_desc), U32, P, SZ, P, SZ, P]
+        L.grid_build_batched_counted.restype = C.c_int
         L.grid_workspace_status.argtypes = [P, C.POINTER(C.c_uint64), P]
         L.grid_workspace_status.restype = C.c_int
         L.grid_tune_set.argtypes = [C.c_char_p, C.c_int]
@@ -390,9 +394,55 @@ def _desc_view(arr) -> np.ndarray:
     return np.frombuffer((C.c_char * C.sizeof(arr)).from_buffer(arr), dtype=_DESC_DTYPE)
 
 
+_FEW = 16   # descriptor arrays up to this length are filled element by element
+
+
+def _desc_bytes(g: GridInput) -> bytes:
+    """A grid's descriptor without outputs, kept while its tensors and bounds stay the same."""
+    key = (g.verts.data_ptr(), g.tris.data_ptr(), g.verts.shape, g.tris.shape, tuple(g.lo), tuple(g.hi), tuple(g.res))
+    cached = getattr(g, "_c_desc", None)
+    if cached is not None and cached[0] == key:
+        return cached[1]
+    d = grid_desc()
+    d.verts_soa = g.verts.data_ptr()
+    d.tris = g.tris.data_ptr()
+    d.nverts = g.nverts
+    d.ntris = g.ntris
+    d.lo[:] = [float(x) for x in g.lo]
+    d.hi[:] = [float(x) for x in g.hi]
+    d.res[:] = [int(x) for x in g.res]
+    b = bytes(d)
+    object.__setattr__(g, "_c_desc", (key, b))
+    return b
+
+
+def _set_outputs(arr, cells: List[int], objs: List[int], ranges: List[int], caps: List[int]):
+    """Write output addresses and pair capacities into a descriptor array."""
+    if len(arr) <= _FEW:
+        for d, c, o, r, k in zip(arr, cells, objs, ranges, caps):
+            out = d.out
+            out.cells = c
+            out.objs = o
+            out.ranges = r
+            out.cap_pairs = k
+        return
+    a = _desc_view(arr)
+    a["cells"] = cells
+    a["objs"] = objs
+    a["ranges"] = ranges
+    a["cap_pairs"] = caps
+
+
 def _descs(inputs: List[GridInput], outs: Optional[List[GridResult]] = None):
-    """ctypes array of grid_desc for the inputs (and outputs), filled column by column."""
+    """ctypes array of grid_desc for the inputs (and outputs): short arrays from each grid's kept
+    descriptor, long ones column by column."""
     n = len(inputs)
+    if 0 < n <= _FEW:
+        arr = (grid_desc * n).from_buffer_copy(b"".join(_desc_bytes(g) for g in inputs))
+        if outs is not None:
+            _set_outputs(arr, [o.cells.data_ptr() for o in outs], [o.objs.data_ptr() for o in outs],
+                         [o.ranges.data_ptr() for o in outs], [o.cells.numel() for o in outs])
+        return arr
     arr = (grid_desc * n)()
     if n == 0:
         return arr
@@ -564,6 +614,50 @@ def build_batched_async(inputs: List[GridInput], outs: List[GridResult], npairs:
                                     _stream(stream))
     _check(st, "grid_build_batched_async")
     for o, c in zip(outs, npairs):
+        o.npairs = int(c)
+
+
+# bits of the status word grid_count_batched_async leaves after the per-grid counts
+COUNT_BAD_INDEX = 1
+COUNT_INTERNAL = 2
+COUNT_OVER_WORKSPACE = 4
+COUNT_OVER_32BIT = 8
+
+
+def count_batched_async(inputs: List[GridInput], ws: Workspace, ws_bytes: int, staging: torch.Tensor,
+                        counts: torch.Tensor, stream=None, descs=None) -> int:
+    """Enqueue the count of a batch into ``ws`` (the first half of a batched build split around its
+    count) and return the pair capacity of the workspace's layout for this batch.
+
+    ``counts`` is a pinned int64 tensor of at least len(inputs) + 1 entries: once the stream has
+    passed this call it holds each grid's NO and then the status word (COUNT_* bits).  ``staging``
+    is a pinned uint8 tensor of at least 2 * grid_batch_staging_size(n) bytes, kept for
+    build_batched_counted.  ``descs``: the inputs' descriptor array when the caller already holds it."""
+    L = lib()
+    n = len(inputs)
+    assert staging.is_pinned() and staging.numel() >= 2 * int(L.grid_batch_staging_size(n))
+    assert counts.is_pinned() and counts.dtype == torch.int64 and counts.numel() >= n + 1
+    assert ws.buf is not None and ws.buf.numel() >= ws_bytes
+    cap = C.c_uint64(0)
+    st = L.grid_count_batched_async(descs if descs is not None else _descs(inputs), n, C.c_void_p(ws.buf.data_ptr()), C.c_size_t(ws_bytes),
+                                    C.c_void_p(staging.data_ptr()), C.c_size_t(staging.numel()),
+                                    C.c_void_p(counts.data_ptr()), C.byref(cap), _stream(stream))
+    _check(st, "grid_count_batched_async")
+    return int(cap.value)
+
+
+def build_batched_counted(inputs: List[GridInput], outs: Optional[List[GridResult]], npairs: List[int], ws: Workspace,
+                          ws_bytes: int, staging: torch.Tensor, stream=None, descs=None):
+    """Enqueue the rest of a batched build counted by count_batched_async into the same workspace, with
+    the same inputs, ``ws_bytes``, staging and stream.  Each output must hold at least its grid's NO
+    (``npairs``).  Errors found on the device are read later with workspace_status(ws).  ``descs``: the
+    descriptor array with the outputs already written (then ``outs`` may be None)."""
+    L = lib()
+    n = len(inputs)
+    st = L.grid_build_batched_counted(descs if descs is not None else _descs(inputs, outs), n, C.c_void_p(ws.buf.data_ptr()), C.c_size_t(ws_bytes),
+                                      C.c_void_p(staging.data_ptr()), C.c_size_t(staging.numel()), _stream(stream))
+    _check(st, "grid_build_batched_counted")
+    for o, c in zip(outs or [], npairs):
         o.npairs = int(c)
 
 

@@ -222,7 +222,7 @@ Layout make_layout(uint64_t ntris, uint64_t cap_pairs, uint64_t ncells_plus_grid
   L.keys_alt2 = take(batched ? cap_pairs * 4 : 0);
   L.vals_alt2 = take(batched ? cap_pairs * 4 : 0);
   L.run = take((ngrids + 1) * sizeof(GridRun));
-  L.npairs_out = take(ngrids * 8);
+  L.npairs_out = take((ngrids + 1) * 8);  // per-grid NO, then the count's status word
   L.splits = take(static_cast<size_t>(L.nmerge_tiles_cap) * 4);
   L.tile_grid = take(batched ? static_cast<size_t>(L.nmerge_tiles_cap) * 4 : 0);
   L.table = take(batched ? ngrids * sizeof(GridDev) : 0);
@@ -301,6 +301,7 @@ struct Build {
   hipStream_t s;
   bool culled;           // plain builds: false intersections removed before the sort
   uint64_t out_cap;      // culled builds: pairs the caller's outputs hold
+  uint64_t layout_cap = ~uint64_t{0};  // pairs the workspace layout holds, checked by the plan
 };
 
 template <bool B>
@@ -335,6 +336,7 @@ int launch_plan(Build& b) {
   a.run = at<GridRun>(b.ws, b.L.run);
   a.npairs_out = at<uint64_t>(b.ws, b.L.npairs_out);
   a.cap_flag = &at<Control>(b.ws, b.L.ctl)->cap_flag;
+  a.cap_total = b.layout_cap;
   a.tfo = at<uint32_t>(b.ws, b.L.tfo);
   a.tfg = at<uint32_t>(b.ws, b.L.tfg);
   a.tfo_work = at<uint4>(b.ws, b.L.tfo_work);
@@ -438,7 +440,8 @@ int launch_expand(Build& b, uint32_t* cells, uint32_t* objs, uint64_t npairs) {
     GB_LAUNCHED();
   }
   if constexpr (B) {
-    // the tiles that straddle grids, skipped above
+    // the tiles that straddle grids, skipped above (a batch of one grid has none)
+    if (b.gs.ngrids < 2) return GRID_OK;
     TraceScope ts(b.s, "expand_straddle");
     auto kern = expand_straddle_kernel<kExpandBlock, kExpandK, RB>;
     kern<<<static_cast<uint32_t>(std::min<uint64_t>(ceil_div(npairs, kExpandTile), 1024)), kExpandBlock, 0, b.s>>>(a);
@@ -624,6 +627,7 @@ int launch_sink(Build& b) {
   SinkArgs a{};
   a.gs = b.gs;
   a.run = at<GridRun>(b.ws, b.L.run);
+  a.cap_flag = &at<Control>(b.ws, b.L.ctl)->cap_flag;
   a.sink = at<GridSink>(b.ws, b.L.sink);
   a.kmap = at<uint2>(b.ws, b.L.kmap);
   a.ksink = at<GridSink>(b.ws, b.L.ksink);
@@ -1058,19 +1062,59 @@ uint32_t batch_chunk(const grid_desc* grids, uint32_t ngrids, uint32_t g0) {
   return std::max(n, 1u);
 }
 
+// The pair capacity a batched layout is made for: the sum of the grids' output
+// capacities, or (builds split into a count and a resumed build) the most pairs
+// the workspace holds, which both halves derive alike from the same inputs.
+constexpr int64_t kCapFromDescs = -1;
+constexpr int64_t kCapFromWorkspace = -2;
+
+// Largest pair capacity whose batched layout fits in ws_bytes (-1: not even an empty one).
+int64_t batch_pair_capacity(const BatchSetup& bs, uint32_t ngrids, size_t ws_bytes) {
+  const Plan plan = make_plan(std::max(1u, bits_for(bs.cells)));
+  auto need = [&](uint64_t cap) { return make_layout(bs.ntris, cap, bs.cells + ngrids, plan, ngrids, true).total; };
+  if (need(0) > ws_bytes) return -1;
+  uint64_t lo = 0, hi = uint64_t{1} << 32;  // the batch's pair indices are 32-bit
+  while (hi - lo > 1) {
+    const uint64_t mid = lo + (hi - lo) / 2;
+    if (need(mid) <= ws_bytes) lo = mid; else hi = mid;
+  }
+  return static_cast<int64_t>(lo);
+}
+
+// Everything of a grid's table entry that the count reads (not its outputs).
+bool same_geometry(const GridDev& a, const GridDev& b) {
+  return a.verts == b.verts && a.tris == b.tris && a.nverts == b.nverts && a.ntris == b.ntris &&
+         a.tri_base == b.tri_base && a.cell_base == b.cell_base && std::memcmp(a.res, b.res, sizeof a.res) == 0 &&
+         std::memcmp(a.lo, b.lo, sizeof a.lo) == 0 && std::memcmp(a.inv, b.inv, sizeof a.inv) == 0;
+}
+
+// counted: when given, the table the batch was counted with (a resumed build),
+// which the new table must match grid for grid before anything is enqueued.
 int prepare_batched(Build& b, BatchSetup& bs, const grid_desc* grids, uint32_t ngrids, void* ws, size_t ws_bytes,
-                    hipStream_t s, bool need_out, void* staging = nullptr, size_t staging_bytes = 0) {
+                    hipStream_t s, bool need_out, void* staging = nullptr, size_t staging_bytes = 0,
+                    int64_t layout = kCapFromDescs, const GridDev* counted = nullptr) {
   int st = setup_batch(grids, ngrids, &bs, need_out);
   if (st) return st;
   if (bs.cells > kMaxBatchCells) return GRID_E_INVAL;
+  if (!ws) return GRID_E_INVAL;
+  if (counted) {
+    for (uint32_t g = 0; g < ngrids; ++g)
+      if (!same_geometry(bs.table[g], counted[g])) return GRID_E_INVAL;
+  }
+  uint64_t cap = bs.cap;
+  if (layout == kCapFromWorkspace) {
+    const int64_t c = batch_pair_capacity(bs, ngrids, ws_bytes);
+    if (c < 0) return GRID_E_NOMEM;
+    cap = static_cast<uint64_t>(c);
+    b.layout_cap = cap;
+  }
   b.ws = ws;
   b.s = s;
   b.ntris = static_cast<uint32_t>(bs.ntris);
   b.batched = true;
   b.plan = make_plan(std::max(1u, bits_for(bs.cells)));
   b.batch_cells = bs.cells;
-  b.L = make_layout(bs.ntris, bs.cap, bs.cells + ngrids, b.plan, ngrids, true);
-  if (!ws) return GRID_E_INVAL;
+  b.L = make_layout(bs.ntris, cap, bs.cells + ngrids, b.plan, ngrids, true);
   if (ws_bytes < b.L.total) return GRID_E_NOMEM;
   b.gs = GridSet{};
   b.gs.table = at<GridDev>(ws, b.L.table);
@@ -1463,6 +1507,53 @@ int grid_build_batched_async(const grid_desc* grids, uint32_t ngrids, void* ws, 
     if ((st = launch_sort<true>(b, nullptr, nullptr, bs.cap))) return st;
   }
   return launch_ranges<true>(b, bs.cells + ngrids + bs.cap);
+}
+
+int grid_count_batched_async(const grid_desc* grids, uint32_t ngrids, void* ws, size_t ws_bytes, void* host_staging,
+                             size_t staging_bytes, uint64_t* counts_host, uint64_t* pair_cap, void* stream) {
+  if (!grids || ngrids == 0 || !host_staging || !counts_host) return GRID_E_INVAL;
+  if (batch_chunk(grids, ngrids, 0) != ngrids) return GRID_E_INVAL;  // packed keys must fit in 32 bits
+  const size_t half = grid_batch_staging_size(ngrids);
+  if (staging_bytes < 2 * half) return GRID_E_NOMEM;
+  Build b{};
+  BatchSetup bs;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // outputs are not known yet: the count checks only the workspace's capacity
+  int st = prepare_batched(b, bs, grids, ngrids, ws, ws_bytes, s, false, host_staging, half, kCapFromWorkspace);
+  if (st) return st;
+  if (pair_cap) *pair_cap = b.layout_cap;
+  if ((st = launch_zero(b.ws, b.L.zero_end, s))) return st;
+  if ((st = launch_count<true>(b))) return st;
+  if ((st = launch_plan<true>(b))) return st;
+  GB_TRY(hipMemcpyAsync(counts_host, at<uint64_t>(b.ws, b.L.npairs_out), (ngrids + 1) * sizeof(uint64_t),
+                        hipMemcpyDeviceToHost, s));
+  return GRID_OK;
+}
+
+int grid_build_batched_counted(const grid_desc* grids, uint32_t ngrids, void* ws, size_t ws_bytes, void* host_staging,
+                               size_t staging_bytes, void* stream) {
+  if (!grids || ngrids == 0 || !host_staging) return GRID_E_INVAL;
+  if (batch_chunk(grids, ngrids, 0) != ngrids) return GRID_E_INVAL;
+  const size_t half = grid_batch_staging_size(ngrids);
+  if (staging_bytes < 2 * half) return GRID_E_NOMEM;
+  Build b{};
+  BatchSetup bs;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the first half of the staging still holds the table the batch was counted with
+  int st = prepare_batched(b, bs, grids, ngrids, ws, ws_bytes, s, true, static_cast<char*>(host_staging) + half, half,
+                           kCapFromWorkspace, static_cast<const GridDev*>(host_staging));
+  if (st) return st;
+  // launch sizes: the outputs' capacities (the kernels read the true counts);
+  // a grid beyond its capacity is caught by the sink kernel, pairs beyond the
+  // workspace by the count's plan, and either way no kernel writes anything
+  const uint64_t n = std::min<uint64_t>(bs.cap, b.layout_cap);
+  if (n > 0) {
+    if (b.plan.sp.passes == 0) return GRID_E_INVAL;
+    if ((st = launch_sort<true>(b, nullptr, nullptr, n))) return st;
+  } else if ((st = launch_sink(b))) {
+    return st;
+  }
+  return launch_ranges<true>(b, bs.cells + ngrids + n);
 }
 
 int grid_workspace_status(const void* ws, uint64_t* npairs_total, void* stream) {

@@ -29,8 +29,9 @@ struct PlanArgs {
   uint32_t ntris;
   uint32_t merge_tile;     // items per merge tile
   GridRun* run;            // [ngrids + 1]; run[ngrids].mtile_base = total merge tiles
-  uint64_t* npairs_out;    // [ngrids] copy of each grid's NO for the host
+  uint64_t* npairs_out;    // [ngrids + 1] each grid's NO for the host, then the count's status word
   uint32_t* cap_flag;      // set when a grid's NO exceeds its capacity
+  uint64_t cap_total;      // pairs the workspace holds (all grids together)
   uint32_t* tfo;           // tile-owner table of the expansion (and tfg, batched) ...
   uint32_t* tfg;
   const uint4* tfo_work;   // ... and the runs of it the count left for this kernel
@@ -82,7 +83,15 @@ __global__ __launch_bounds__(Block) void plan_kernel(PlanArgs a) {
     if (g < G) a.run[g].mtile_base = carry + ex;
     carry += tot;
   }
-  if (threadIdx.x == 0) a.run[G].mtile_base = carry;
+  if (threadIdx.x == 0) {
+    a.run[G].mtile_base = carry;
+    if (total > a.cap_total) atomicOr(a.cap_flag, 1u);
+  }
+  if (a.npairs_out) {
+    // the status word: the count's error bits, then the capacity flags shifted by 2
+    __syncthreads();
+    if (threadIdx.x == 0) a.npairs_out[G] = a.ctl->error | (static_cast<uint64_t>(atomicOr(a.cap_flag, 0u)) << 2);
+  }
 }
 
 // Where the last radix pass of a batched build writes each grid's pairs: its
@@ -103,6 +112,7 @@ struct alignas(16) GridSink {
 struct SinkArgs {
   GridSet gs;
   const GridRun* run;
+  uint32_t* cap_flag;      // set when a grid's NO exceeds the capacity of its outputs
   GridSink* sink;          // [ngrids]
   uint2* kmap;             // [nbuckets] grids of the bucket's first and last key
   GridSink* ksink;         // [nbuckets] the sink of the bucket's first grid, straddles set if it has several
@@ -127,6 +137,9 @@ __global__ __launch_bounds__(Block) void sink_kernel(SinkArgs a) {
   const uint32_t first = blockIdx.x * Block + threadIdx.x;
   for (uint32_t g = first; g < a.gs.ngrids; g += stride) {
     const GridDev& d = a.gs.table[g];
+    // the outputs may have been given after the count (a build resumed from its
+    // count): their capacities are checked again here, before any pass writes
+    if (a.run[g].npairs > d.cap_pairs) atomicOr(a.cap_flag, 1u);
     GridSink k;
     k.cells = d.out_cells;
     k.objs = d.out_objs;

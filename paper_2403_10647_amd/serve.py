@@ -1,25 +1,31 @@
 """Continuous-batching server for grid builds.
 
-Requests (a scene each, already in device memory) arrive over time.  On
-arrival a request is counted (CountCells + ExclusiveSum, Algorithm 1), which
-predicts its pair count NO exactly; from NO and the cell count R follow the
-bytes its outputs need, and the request is admitted when they fit in the
-device-memory budget next to the resident workspaces.  Admitted requests wait
-in a FIFO queue; whenever a slot (a stream with its own resident workspace and
-pinned staging) is free, the requests at the head of the queue are built
-together as one batched build with no host synchronisation.  Several slots
-are in flight at once, so requests that arrive while others are on the GPU
-overlap with them on the device.  When a slot's completion event has passed,
-its requests are complete: their latency runs from the scheduled arrival to
-the moment the host observes the completion.
+Requests (a scene each, already in device memory) arrive over time.  Whenever
+a slot (a stream with its own resident workspace and pinned staging) is free,
+the requests that have arrived are counted there together (CountCells +
+ExclusiveSum, Algorithm 1) without a host wait.  The count predicts each
+request's pair count NO exactly; from NO and the cell count R follow the bytes
+its outputs need.  When the slot's count has completed and those bytes fit in
+the device-memory budget next to the resident workspaces, the outputs are
+allocated and the same build resumes from its count (radix passes and ranges
+only), again without a host wait.  A request larger than the whole budget is
+rejected.  Several slots are in flight at once, so requests that arrive while
+others are on the GPU overlap with them on the device.  When a slot's
+completion event has passed, its requests are complete: their latency runs from
+the scheduled arrival to the moment the host observes the completion.
+
+Counted batches that cannot resume (a bad request among them, more pairs than
+the slot's workspace holds, outputs above the budget) fall back to a FIFO
+queue of counted requests, built as whole batched builds (count included)
+that form_batch sizes to the budget, the pair cap and the workspace.
 
 Every output can be compared on the device with a reference output of the same
 scene (its stand-alone build); mismatches are counted per slot and read back
 once at the end, off the timed path.
 
-Batch formation (``form_batch``) is pure host logic: FIFO order, a cap on
-grids and pairs per batch, the batch's cells within one 32-bit key space, and
-the byte budget.
+Batch formation (``form_batch``, ``form_count_batch``) is pure host logic: FIFO
+order, a cap on grids (and pairs) per batch, the batch's cells within one
+32-bit key space, and the byte budget.
 """
 from __future__ import annotations
 
@@ -99,18 +105,42 @@ def form_batch(queue: Sequence[Request], free_bytes: int, max_grids: int, max_pa
     return n
 
 
+def form_count_batch(arrived: Sequence[Request], max_grids: int, max_pairs: int, pairs_per_tri: float) -> int:
+    """How many requests from the head of the arrival FIFO are counted together (at least one):
+    at most max_grids, their cells within one 32-bit key space, and, unless the batch is empty,
+    at most max_pairs pairs predicted at pairs_per_tri pairs per triangle (NO is only known
+    after the count)."""
+    n = 0
+    cells = 0
+    pairs = 0.0
+    for r in arrived:
+        p = r.inp.ntris * pairs_per_tri
+        if n > 0 and (n >= max_grids or cells + r.inp.ncells > MAX_BATCH_CELLS or pairs + p > max_pairs):
+            break
+        n += 1
+        cells += r.inp.ncells
+        pairs += p
+    return n
+
+
 class _Slot:
     def __init__(self, device, ws_bytes: int, max_grids: int):
         self.stream = torch.cuda.Stream(device=device)
         self.ws = G.Workspace(device)
         self.ws.get(ws_bytes)
         self.ws_bytes = ws_bytes
-        self.staging = torch.empty(int(G.lib().grid_batch_staging_size(max_grids)), dtype=torch.uint8,
+        # two tables: the counted one stays while the resumed build copies the second
+        self.staging = torch.empty(2 * int(G.lib().grid_batch_staging_size(max_grids)), dtype=torch.uint8,
                                    pin_memory=True)
+        self.counts = torch.zeros(max_grids + 1, dtype=torch.int64, pin_memory=True)
+        self.counted = torch.cuda.Event()
+        self.counting: List[Request] = []    # requests counted on this slot, not yet built
         self.event = torch.cuda.Event()
         self.batch: List[Request] = []
         self.bytes = 0
         self.arena = None
+        self.pair_at: List[int] = []         # each request's first pair in the arena
+        self.descs = None                    # descriptor array of the counted batch
         self.mismatch = torch.zeros((), dtype=torch.int64, device=device)
 
 
@@ -160,6 +190,9 @@ class Server:
         self.count_stream = torch.cuda.Stream(device=self.device)
         self.count_ws = G.Workspace(self.device)
         self.out_budget = self.budget - self.ws_bytes * nslots
+        # pairs per triangle seen so far (sizes count batches before their NO is known)
+        self.seen_tris = 0
+        self.seen_pairs = 0
 
     # -- admission count -----------------------------------------------------
     def _count(self, new: List[Request]) -> List[int]:
@@ -177,26 +210,113 @@ class Server:
                 out.append(e.status)
         return out
 
-    # -- one batch ---------------------------------------------------------
+    # -- outputs -----------------------------------------------------------
+    def _outputs(self, slot: _Slot, inputs: List[G.GridInput], caps: List[int]):
+        """One device allocation (on the slot's stream) holding every grid's cells, objs and ranges:
+        (arena (cells, objs, ranges), each grid's first pair and first range word)."""
+        tot_pairs = sum(max(c, 1) for c in caps)
+        tot_ranges = sum(2 * g.ncells for g in inputs)
+        with torch.cuda.stream(slot.stream):
+            buf = torch.empty(2 * tot_pairs + tot_ranges, dtype=torch.int32, device=self.device)
+        arena = (buf[:tot_pairs], buf[tot_pairs:2 * tot_pairs], buf[2 * tot_pairs:])
+        pair_at, range_at = [], []
+        p = q = 0
+        for g, c in zip(inputs, caps):
+            pair_at.append(p)
+            range_at.append(q)
+            p += max(c, 1)
+            q += 2 * g.ncells
+        return arena, pair_at, range_at
+
+    def _out_descs(self, arr, inputs, caps, arena, pair_at, range_at):
+        """Write the outputs' addresses into the descriptor array ``arr``."""
+        c0, o0, r0 = (x.data_ptr() for x in arena)
+        G._set_outputs(arr, [c0 + 4 * p for p in pair_at], [o0 + 4 * p for p in pair_at],
+                       [r0 + 4 * q for q in range_at], [max(c, 1) for c in caps])
+
+    def _started(self, slot: _Slot, batch: List[Request], arena, pair_at, range_at):
+        slot.event.record(slot.stream)
+        cells, objs, ranges = arena
+        for r, p, q in zip(batch, pair_at, range_at):
+            if self.keep:
+                n = max(r.npairs, 1)
+                r.result = G.GridResult(cells[p:p + n], objs[p:p + n], ranges[q:q + 2 * r.inp.ncells], r.npairs)
+        slot.batch = batch
+        slot.arena = arena
+        slot.pair_at = pair_at
+        slot.bytes = sum(r.out_bytes for r in batch)
+
+    # -- a batch counted on its slot, then resumed ---------------------------
+    def _count_on(self, slot: _Slot, batch: List[Request]) -> bool:
+        """Enqueue the count of ``batch`` on ``slot``; False if the workspace cannot hold even the count."""
+        inputs = [r.inp for r in batch]
+        arr = G._descs(inputs)
+        try:
+            G.count_batched_async(inputs, slot.ws, slot.ws_bytes, slot.staging, slot.counts, slot.stream, descs=arr)
+        except G.GridError:
+            return False
+        slot.counted.record(slot.stream)
+        slot.counting = batch
+        slot.descs = arr
+        return True
+
+    def _resume(self, slot: _Slot, free_bytes: int):
+        """Admission of the batch counted on ``slot`` once its count has completed.
+
+        Returns (state, requests): "built" (the build resumed on the slot), "wait" (its outputs do not
+        fit in free_bytes yet), "failed" (the resumed build was refused: the requests carry its
+        status), or "fallback" (the requests are handed back, counted where possible, for the
+        whole-batch path; their npairs is set, or their status if their own count failed)."""
+        batch = slot.counting
+        k = len(batch)
+        c = slot.counts[:k + 1].tolist()
+        status = c[k]
+        if status & (G.COUNT_BAD_INDEX | G.COUNT_INTERNAL | G.COUNT_OVER_32BIT):
+            # a bad request among them, or 32-bit pair starts that wrapped: counted again one by
+            # one, so that a bad request fails alone
+            slot.counting = []
+            for r, n in zip(batch, self._count(batch)):
+                if n < 0:
+                    r.status = n
+                else:
+                    r.npairs = n
+                    r.out_bytes = output_bytes(n, r.inp.ncells)
+            return "fallback", batch
+        for r, n in zip(batch, c[:k]):
+            r.npairs = int(n)
+            r.out_bytes = output_bytes(r.npairs, r.inp.ncells)
+            self.seen_tris += r.inp.ntris
+            self.seen_pairs += r.npairs
+        need = sum(r.out_bytes for r in batch)
+        if status or need > self.out_budget:
+            slot.counting = []
+            return "fallback", batch
+        if need > free_bytes:
+            return "wait", []
+        slot.counting = []
+        inputs = [r.inp for r in batch]
+        caps = c[:k]
+        arena, pair_at, range_at = self._outputs(slot, inputs, caps)
+        self._out_descs(slot.descs, inputs, caps, arena, pair_at, range_at)
+        try:
+            G.build_batched_counted(inputs, None, caps, slot.ws, slot.ws_bytes, slot.staging, slot.stream,
+                                    descs=slot.descs)
+        except G.GridError as e:
+            for r in batch:
+                r.status = e.status
+            return "failed", batch
+        self._started(slot, batch, arena, pair_at, range_at)
+        return "built", batch
+
+    # -- one whole batch (count included) --------------------------------------
     def _launch(self, slot: _Slot, batch: List[Request]) -> List[Request]:
         """Launch ``batch`` on ``slot``; returns the requests that could not be launched."""
         inputs = [r.inp for r in batch]
         while True:
             caps = [r.npairs for r in batch]
-            with torch.cuda.stream(slot.stream):
-                tot_pairs = sum(max(c, 1) for c in caps)
-                tot_ranges = sum(2 * g.ncells for g in inputs)
-                cells = torch.empty(tot_pairs, dtype=torch.int32, device=self.device)
-                objs = torch.empty(tot_pairs, dtype=torch.int32, device=self.device)
-                ranges = torch.empty(tot_ranges, dtype=torch.int32, device=self.device)
-            outs = []
-            p = q = 0
-            for g, c in zip(inputs, caps):
-                n = max(c, 1)
-                outs.append(G.GridResult(cells[p:p + n], objs[p:p + n], ranges[q:q + 2 * g.ncells], 0))
-                p += n
-                q += 2 * g.ncells
-            arr = G._descs(inputs, outs)
+            arena, pair_at, range_at = self._outputs(slot, inputs, caps)
+            arr = G._descs(inputs)
+            self._out_descs(arr, inputs, caps, arena, pair_at, range_at)
             need = int(G.lib().grid_workspace_size_batched(arr, len(inputs)))
             if need <= slot.ws_bytes or len(batch) == 1:
                 break
@@ -211,30 +331,24 @@ class Server:
             for r in batch:
                 r.status = st
             return []
-        slot.event.record(slot.stream)
-        if self.refs is not None:
-            self._verify(slot, batch, outs, cells, objs, ranges)
-        for r, o, c in zip(batch, outs, caps):
-            o.npairs = c
-            r.result = o
-        slot.batch = batch
-        slot.arena = (cells, objs, ranges)
-        slot.bytes = sum(r.out_bytes for r in batch)
+        self._started(slot, batch, arena, pair_at, range_at)
         return []
 
-    def _verify(self, slot, batch, outs, cells, objs, ranges):
+    def _verify(self, slot: _Slot):
+        """Compare the slot's outputs with the references on the device (queued after the build on the
+        slot's stream, once its requests are complete, so that it adds to no request's latency)."""
+        cells, objs, ranges = slot.arena
         with torch.cuda.stream(slot.stream):
             rc, ro, rr = [], [], []
-            for r, o in zip(batch, outs):
+            for r, p in zip(slot.batch, slot.pair_at):
                 ref = self.refs[r.key]
-                n = max(r.npairs, 1)
                 if r.npairs == 0:
-                    # the empty slot of an empty grid holds no output: compare it with itself
-                    rc.append(o.cells)
-                    ro.append(o.objs)
+                    # the one-pair slot of an empty grid holds no output: compare it with itself
+                    rc.append(cells[p:p + 1])
+                    ro.append(objs[p:p + 1])
                 else:
-                    rc.append(ref.cells[:n])
-                    ro.append(ref.objs[:n])
+                    rc.append(ref.cells[:r.npairs])
+                    ro.append(ref.objs[:r.npairs])
                 rr.append(ref.ranges)
             slot.mismatch += (cells != torch.cat(rc)).sum() + (objs != torch.cat(ro)).sum() + \
                 (ranges != torch.cat(rr)).sum()
@@ -244,7 +358,10 @@ class Server:
         for r in slot.batch:
             r.done = now
             r.status = st
-            if not self.keep:
+        if self.refs is not None and st == G.GRID_OK:
+            self._verify(slot)
+        if not self.keep:
+            for r in slot.batch:
                 r.result = None
         slot.batch = []
         slot.arena = None
@@ -259,7 +376,9 @@ class Server:
         for s in self.slots:
             s.mismatch.zero_()
         torch.cuda.synchronize(self.device)
-        queue: List[Request] = []
+        arrived: List[Request] = []    # not yet counted, FIFO
+        queue: List[Request] = []      # counted, for whole batched builds, FIFO
+        counted: List[_Slot] = []      # slots holding a counted batch, in count order
         used = 0
         peak = 0
         peak_slots = 0
@@ -268,62 +387,93 @@ class Server:
         batches = 0
         batched = 0
         t0 = clock()
+
+        def settle(r: Request) -> int:
+            """A counted request from a failed resume: queued, or finished (failed or above the budget)."""
+            if r.status != G.GRID_OK:
+                r.done = clock() - t0
+                return 1
+            if r.out_bytes > self.out_budget:
+                r.status = G.GRID_E_NOMEM
+                r.done = clock() - t0
+                return 1
+            queue.append(r)
+            return 0
+
         while finished < n:
             now = clock() - t0
-            # arrivals: count them together, on their own stream
-            j = nxt
-            while j < n and reqs[j].arrival <= now:
-                j += 1
-            if j > nxt:
-                new = reqs[nxt:j]
-                nxt = j
-                caps = self._count(new)
-                for k, r in enumerate(new):
-                    if caps[k] < 0:            # this request's own count failed (e.g. a bad vertex index)
-                        r.status = caps[k]
-                        r.done = clock() - t0
-                        finished += 1
-                        continue
-                    r.npairs = caps[k]
-                    r.out_bytes = output_bytes(r.npairs, r.inp.ncells)
-                    if r.out_bytes > self.out_budget:
-                        r.status = G.GRID_E_NOMEM
-                        r.done = clock() - t0
-                        finished += 1
-                    else:
-                        queue.append(r)
+            while nxt < n and reqs[nxt].arrival <= now:
+                arrived.append(reqs[nxt])
+                nxt += 1
             # completions
             for s in self.slots:
                 if s.batch and s.event.query():
                     k = len(s.batch)
                     used -= self._finish(s, clock() - t0)
                     finished += k
-            # launches
-            for s in self.slots:
-                if s.batch or not queue:
-                    continue
-                k = form_batch(queue, self.out_budget - used, self.max_grids, self.max_pairs)
-                if k == 0:
+            # counted batches, in count order: resume when their outputs fit
+            while counted and counted[0].counted.query():
+                s = counted[0]
+                state, batch = self._resume(s, self.out_budget - used)
+                if state == "wait":
                     break
-                batch = queue[:k]
-                self._launch(s, batch)
-                launched = len(s.batch)
-                if launched == 0:
-                    # the head could not be built (too large for a workspace, or an error)
-                    r = queue.pop(0)
-                    r.done = clock() - t0
-                    finished += 1
+                counted.pop(0)
+                if state == "built":
+                    used += s.bytes
+                    peak = max(peak, used)
+                    peak_slots = max(peak_slots, sum(1 for x in self.slots if x.batch))
+                    batches += 1
+                    batched += len(batch)
+                elif state == "failed":
+                    for r in batch:
+                        r.done = clock() - t0
+                    finished += len(batch)
+                else:
+                    finished += sum(settle(r) for r in batch)
+            # whole batched builds of the requests handed back, then counts of new arrivals
+            for s in self.slots:
+                if s.batch or s.counting:
                     continue
-                del queue[:launched]
-                used += s.bytes
-                peak = max(peak, used)
-                peak_slots = max(peak_slots, sum(1 for x in self.slots if x.batch))
-                batches += 1
-                batched += launched
-            if not queue and all(not s.batch for s in self.slots) and nxt < n:
+                if queue:
+                    k = form_batch(queue, self.out_budget - used, self.max_grids, self.max_pairs)
+                    if k == 0:
+                        continue
+                    self._launch(s, queue[:k])
+                    launched = len(s.batch)
+                    if launched == 0:
+                        # the head could not be built (too large for a workspace, or an error)
+                        r = queue.pop(0)
+                        r.done = clock() - t0
+                        finished += 1
+                        continue
+                    del queue[:launched]
+                    used += s.bytes
+                    peak = max(peak, used)
+                    peak_slots = max(peak_slots, sum(1 for x in self.slots if x.batch))
+                    batches += 1
+                    batched += launched
+                elif arrived:
+                    ppt = 1.25 * self.seen_pairs / self.seen_tris if self.seen_tris else 16.0
+                    k = form_count_batch(arrived, self.max_grids, self.max_pairs, ppt)
+                    batch = arrived[:k]
+                    del arrived[:k]
+                    if self._count_on(s, batch):
+                        counted.append(s)
+                    else:
+                        # the workspace cannot hold even their count: counted apart, built whole
+                        for r, c in zip(batch, self._count(batch)):
+                            if c < 0:
+                                r.status = c
+                            else:
+                                r.npairs = c
+                                r.out_bytes = output_bytes(c, r.inp.ncells)
+                        finished += sum(settle(r) for r in batch)
+            idle = not arrived and not queue and not counted and all(not s.batch for s in self.slots)
+            if idle and nxt < n:
+                # sleep until a millisecond before the next arrival (sleeps overshoot), then poll
                 wait = reqs[nxt].arrival - (clock() - t0)
-                if wait > 2e-4:
-                    time.sleep(wait - 1e-4)
+                if wait > 2e-3:
+                    time.sleep(wait - 1e-3)
         t_end = clock() - t0
         torch.cuda.synchronize(self.device)
         mism = int(sum(int(s.mismatch.item()) for s in self.slots)) if self.refs is not None else 0
@@ -366,6 +516,13 @@ def make_requests(pool: Sequence[G.GridInput], rate: float, duration: float, see
         nb = int(math.ceil(duration / big_every))
         reqs += [Request(m + b, 0.0 if burst else b * big_every, big, big_key) for b in range(nb)]
     return reqs
+
+
+def spaced_requests(pool: Sequence[G.GridInput], gap: float, count: int, seed: int) -> List[Request]:
+    """``count`` requests drawn uniformly from ``pool``, one every ``gap`` seconds (request keys index the pool)."""
+    rng = np.random.default_rng(np.random.SeedSequence(entropy=seed, spawn_key=(4, 3)))
+    keys = rng.integers(0, len(pool), size=count)
+    return [Request(i, i * gap, pool[int(k)], int(k)) for i, k in enumerate(keys)]
 
 
 def plain_builds_per_s(requests: Sequence[Request], ws: Optional[G.Workspace] = None) -> Dict[str, float]:

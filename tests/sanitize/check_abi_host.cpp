@@ -68,6 +68,28 @@ int main() {
   d[1].res[2] = 0;
   CHECK(grid_workspace_size_batched(d, 2) == 0, "batched sizing rejects a bad grid");
   CHECK(grid_build_batched(d, 0, dummy, 16, nullptr) == GRID_E_INVAL, "batched: no grids");
+  // the batched build split around its count: everything here is refused on the host
+  d[1].res[2] = 8;
+  d[0].ntris = d[1].ntris = 1;
+  d[0].verts_soa = d[1].verts_soa = reinterpret_cast<const float*>(dummy);
+  d[0].tris = d[1].tris = reinterpret_cast<const uint32_t*>(dummy);
+  const size_t half = grid_batch_staging_size(2);
+  static unsigned char staging[1 << 12];
+  uint64_t counts[3] = {0, 0, 0}, cap = 7;
+  CHECK(2 * half <= sizeof(staging), "staging size");
+  CHECK(grid_count_batched_async(d, 2, dummy, 16, staging, 2 * half, counts, &cap, nullptr) == GRID_E_NOMEM,
+        "split count: workspace below the count");
+  CHECK(grid_count_batched_async(d, 2, dummy, 1 << 20, staging, half, counts, &cap, nullptr) == GRID_E_NOMEM,
+        "split count: one staging table");
+  CHECK(grid_count_batched_async(d, 2, dummy, 1 << 20, staging, 2 * half, nullptr, &cap, nullptr) == GRID_E_INVAL,
+        "split count: no counts");
+  CHECK(cap == 7, "split count: no capacity reported on failure");
+  memset(staging, 0, sizeof(staging));
+  for (int g = 0; g < 2; ++g) { d[g].out.cells = dummy; d[g].out.objs = dummy; d[g].out.cap_pairs = 4; }
+  CHECK(grid_build_batched_counted(d, 2, dummy, 1 << 20, staging, 2 * half, nullptr) == GRID_E_INVAL,
+        "split build: grids other than the counted ones");
+  CHECK(grid_build_batched_counted(d, 2, dummy, 1 << 20, staging, half, nullptr) == GRID_E_NOMEM,
+        "split build: one staging table");
   uint64_t tot = 0;
   CHECK(grid_scan_u32(nullptr, nullptr, nullptr, 0, GRID_SCAN_EXCLUSIVE_SUM, nullptr, 0, &tot, nullptr) == GRID_OK,
         "scan of nothing");

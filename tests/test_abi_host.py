@@ -126,6 +126,42 @@ def test_batched_validation_on_host(G):
     assert L.grid_build_batched(arr, 2, C.c_void_p(16), 64, None) == G.GRID_E_NOMEM
 
 
+def test_split_batched_build_validates_on_host(G):
+    # the count and the resumed build of a batched build split around its count:
+    # argument checks, the workspace capacity and the counted-table match all
+    # come before anything is enqueued
+    L = G.lib()
+    arr = (G.grid_desc * 2)()
+    for d in arr:
+        d.verts_soa, d.tris, d.nverts, d.ntris = 16, 16, 3, 1
+        d.lo[:] = [0, 0, 0]
+        d.hi[:] = [1, 1, 1]
+        d.res[:] = [4, 4, 4]
+        d.out.cells, d.out.objs, d.out.ranges, d.out.cap_pairs = 16, 16, 16, 4
+    half = L.grid_batch_staging_size(2)
+    staging = (C.c_ubyte * (2 * half))()
+    counts = (C.c_uint64 * 3)()
+    cap = C.c_uint64(123)
+    P = C.c_void_p(16)
+    count = L.grid_count_batched_async
+    assert count(None, 0, P, 1 << 20, staging, 2 * half, counts, C.byref(cap), None) == G.GRID_E_INVAL
+    assert count(arr, 2, P, 1 << 20, None, 2 * half, counts, C.byref(cap), None) == G.GRID_E_INVAL
+    assert count(arr, 2, P, 1 << 20, staging, 2 * half, None, C.byref(cap), None) == G.GRID_E_INVAL
+    assert count(arr, 2, P, 1 << 20, staging, half, counts, C.byref(cap), None) == G.GRID_E_NOMEM  # one table only
+    assert count(arr, 2, P, 64, staging, 2 * half, counts, C.byref(cap), None) == G.GRID_E_NOMEM  # not even the count
+    assert count(arr, 2, None, 1 << 20, staging, 2 * half, counts, C.byref(cap), None) == G.GRID_E_INVAL
+    assert cap.value == 123                        # nothing reported on failure
+    arr[1].res[:] = [4, 0, 4]
+    assert count(arr, 2, P, 1 << 20, staging, 2 * half, counts, C.byref(cap), None) == G.GRID_E_INVAL
+    arr[1].res[:] = [4, 4, 4]
+    resume = L.grid_build_batched_counted
+    assert resume(arr, 2, P, 1 << 20, staging, half, None) == G.GRID_E_NOMEM
+    # the first half of the staging is not the table of these grids (all zero): refused
+    assert resume(arr, 2, P, 1 << 20, staging, 2 * half, None) == G.GRID_E_INVAL
+    arr[0].out.objs = 0                            # an output missing
+    assert resume(arr, 2, P, 1 << 20, staging, 2 * half, None) == G.GRID_E_INVAL
+
+
 def test_trace_read_without_launches(G):
     G.trace_enable(True)
     assert G.trace_read() == {}

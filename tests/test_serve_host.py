@@ -8,8 +8,9 @@ from paper_2403_10647_amd import serve  # noqa: E402
 
 
 class _Inp:
-    def __init__(self, ncells):
+    def __init__(self, ncells, ntris=0):
         self.ncells = ncells
+        self.ntris = ntris
 
 
 def _req(i, npairs, ncells):
@@ -52,6 +53,23 @@ def test_form_batch_keeps_keys_within_32_bits():
     assert serve.form_batch(q, 1 << 50, 512, 1 << 30) == 4
     q = [_req(i, 1, 1 << 10) for i in range(100)] + [_req(100, 1, 1 << 30)] * 4
     assert serve.form_batch(q, 1 << 50, 512, 1 << 30) == 103   # 100 * 2^10 + 3 * 2^30 < 2^32
+
+
+def _arr(i, ntris, ncells=64):
+    return serve.Request(i, 0.0, _Inp(ncells, ntris))
+
+
+def test_form_count_batch_limits():
+    # before the count only the triangles are known: pairs are predicted at a pairs-per-triangle rate
+    a = [_arr(i, 1000) for i in range(10)]
+    assert serve.form_count_batch(a, 512, 1 << 30, 4.0) == 10
+    assert serve.form_count_batch(a, 3, 1 << 30, 4.0) == 3                # grid cap
+    assert serve.form_count_batch(a, 512, 12_000, 4.0) == 3               # 3 x 4000 predicted pairs fit
+    assert serve.form_count_batch(a, 512, 11_999, 4.0) == 2
+    assert serve.form_count_batch(a, 512, 100, 4.0) == 1                  # the head always goes
+    assert serve.form_count_batch([], 512, 1 << 30, 4.0) == 0
+    q = [_arr(i, 1, 1 << 30) for i in range(5)]
+    assert serve.form_count_batch(q, 512, 1 << 30, 4.0) == 4              # 32-bit cell space
 
 
 def test_poisson_arrivals():
