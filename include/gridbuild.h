@@ -123,11 +123,14 @@ int grid_build(const float *verts_soa, uint32_t nverts, const uint32_t *tris, ui
  * vertex coordinate lies outside [0, res] (or is NaN), or when its box holds
  * at most two cells.  The kept pairs are sorted and ranged as in grid_build.
  * box_cap bounds the box pair count (grid_count's NO): ws must hold
- * grid_workspace_size(ntris, box_cap, res) bytes, and out->cap_pairs may be
+ * grid_workspace_size_culled(ntris, box_cap, res) bytes (the plain build's
+ * workspace plus 176 bytes per triangle, where each triangle's axes and
+ * bounds are computed once for all its pairs), and out->cap_pairs may be
  * smaller than box_cap (fewer pairs are kept).  *box_npairs (host) receives
  * the box pair count and out->npairs the kept count.  GRID_E_CAPACITY when
  * the box pairs exceed box_cap (out->npairs = 0) or the kept pairs exceed
  * out->cap_pairs (out->npairs = the kept count).  Synchronizes stream once. */
+size_t grid_workspace_size_culled(uint32_t ntris, uint64_t box_cap, const uint32_t res[3]);
 int grid_build_culled(const float *verts_soa, uint32_t nverts, const uint32_t *tris, uint32_t ntris,
                       const float lo[3], const float hi[3], const uint32_t res[3],
                       void *ws, size_t ws_bytes, uint64_t box_cap, grid_out *out, uint64_t *box_npairs,

@@ -33,6 +33,7 @@ SCAN_SEGMENTED_EXCLUSIVE_SUM = 2
 
 EXPORTS = (
     "grid_strerror", "grid_workspace_size", "grid_count", "grid_build", "grid_build_static", "grid_build_culled", "grid_expand",
+    "grid_workspace_size_culled",
     "grid_workspace_size_batched", "grid_count_batched", "grid_build_batched",
     "grid_sort_workspace_size", "grid_sort_pairs", "grid_scan_workspace_size", "grid_scan_u32",
     "grid_trace_enable", "grid_trace_read", "grid_tune_set", "grid_tune_get", "grid_sort_plan",
@@ -85,6 +86,8 @@ def lib():
         L.grid_strerror.restype = C.c_char_p
         L.grid_workspace_size.argtypes = [U32, U64, U3]
         L.grid_workspace_size.restype = SZ
+        L.grid_workspace_size_culled.argtypes = [U32, U64, U3]
+        L.grid_workspace_size_culled.restype = SZ
         L.grid_count.argtypes = [P, U32, P, U32, F3, F3, U3, P, SZ, P, C.POINTER(C.c_uint64), P]
         L.grid_build.argtypes = [P, U32, P, U32, F3, F3, U3, P, SZ, C.POINTER(grid_out), P]
         L.grid_build_static.argtypes = [P, U32, P, U32, F3, F3, U3, C.POINTER(grid_out), P]
@@ -245,6 +248,11 @@ def workspace_size(ntris: int, cap_pairs: int, res) -> int:
     return n
 
 
+def workspace_size_culled(ntris: int, box_cap: int, res) -> int:
+    """Workspace of grid_build_culled: the plain build's plus each triangle's test record."""
+    return int(lib().grid_workspace_size_culled(ntris, box_cap, _u3(res)))
+
+
 def count(g: GridInput, ws: Optional[Workspace] = None, with_start: bool = False, stream=None):
     """CountCells + ExclusiveSum: (NO, start[T] or None)."""
     L = lib()
@@ -303,7 +311,7 @@ def build_culled(g: GridInput, box_cap: Optional[int] = None, out: Optional[Grid
         out = GridResult(torch.empty(max(box_cap, 1), dtype=torch.int32, device=dev),
                          torch.empty(max(box_cap, 1), dtype=torch.int32, device=dev),
                          torch.empty(2 * g.ncells, dtype=torch.int32, device=dev), 0)
-    wp, wn = ws.ptr_size(workspace_size(g.ntris, box_cap, g.res))
+    wp, wn = ws.ptr_size(workspace_size_culled(g.ntris, box_cap, g.res))
     o = grid_out(out.cells.data_ptr(), out.objs.data_ptr(), out.ranges.data_ptr(), int(out.cells.numel()), 0)
     nbox = C.c_uint64(0)
     st = L.grid_build_culled(*_input_args(g), wp, wn, C.c_uint64(box_cap), C.byref(o), C.byref(nbox), _stream(stream))
@@ -344,7 +352,7 @@ class CulledBuild:
     def __init__(self, g: GridInput, out: GridResult, box_cap: int, ws: Optional[Workspace] = None, stream=None):
         self.g, self.out = g, out
         self.ws = ws or default_workspace(g.verts.device)
-        wp, wn = self.ws.ptr_size(workspace_size(g.ntris, box_cap, g.res))
+        wp, wn = self.ws.ptr_size(workspace_size_culled(g.ntris, box_cap, g.res))
         self._o = grid_out(out.cells.data_ptr(), out.objs.data_ptr(), out.ranges.data_ptr(), int(out.cells.numel()), 0)
         self._nbox = C.c_uint64(0)
         self._fn = lib().grid_build_culled

@@ -12,9 +12,11 @@
 // box when a vertex lies outside [0, res] on some axis (or is NaN), or when
 // its box holds at most two cells (it touches them all).
 //
-// The culled expansion tests each box pair, keeps the survivors in object
-// order (a tile scan plus a decoupled look-back over tiles), and feeds the
-// kept count to the radix sort and the ranges.
+// Each triangle's axes and bounds are computed once, by one thread, into a
+// record of the workspace; the culled expansion then tests each box pair
+// against its triangle's record, keeps the survivors in object order (a tile
+// scan plus a decoupled look-back over tiles), and feeds the kept count to the
+// radix sort and the ranges.
 #pragma once
 
 #include "ranges.hpp"
@@ -80,23 +82,39 @@ GB_DEV void cull_axes(const float u[3][3], CullAxes& c) {
   }
 }
 
-// True when the triangle touches the widened cell with lower corner (x, y, z).
-GB_DEV bool cull_touches(const CullAxes& c, float x, float y, float z) {
+// A triangle's record in the workspace, in 16-byte groups that the culled
+// expansion loads one at a time: the normal axis with its bounds and whether
+// the test applies, then per edge its three axes (edge x X, edge x Y, edge x Z:
+// their two non-zero components, for (y, z), (x, z) and (x, y)) and bounds.
+struct CullEdge {
+  float c[3][2];
+  float above[3], below[3];
+};
+
+struct alignas(16) CullRecord {
+  float n[3], n_above;
+  float n_below;
+  uint32_t test;            // 1: the test applies (else only this word is written)
+  float pad[2];
+  CullEdge e[3];
+};
+static_assert(sizeof(CullRecord) == 176, "eleven 16-byte words");
+constexpr int kRecWords4 = 11;
+
+// The normal axis separates the widened cell with lower corner (x, y, z).
+GB_DEV bool normal_separates(const float n[3], float above, float below, float x, float y, float z) {
   const float b[3] = {x, y, z};
-  const float cn = dot3f(c.n, b);
-  // every axis is evaluated (no early exit): the result is the same, and the
-  // wave does not branch per axis
-  bool sep = (cn > c.n_above) | (cn < c.n_below);
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const float cx = __fadd_rn(__fmul_rn(c.e[3 * i + 0][0], y), __fmul_rn(c.e[3 * i + 0][1], z));
-    const float cy = __fadd_rn(__fmul_rn(c.e[3 * i + 1][0], x), __fmul_rn(c.e[3 * i + 1][1], z));
-    const float cz = __fadd_rn(__fmul_rn(c.e[3 * i + 2][0], x), __fmul_rn(c.e[3 * i + 2][1], y));
-    sep = sep | (cx > c.e_above[3 * i + 0]) | (cx < c.e_below[3 * i + 0]);
-    sep = sep | (cy > c.e_above[3 * i + 1]) | (cy < c.e_below[3 * i + 1]);
-    sep = sep | (cz > c.e_above[3 * i + 2]) | (cz < c.e_below[3 * i + 2]);
-  }
-  return !sep;
+  const float cn = dot3f(n, b);
+  return (cn > above) | (cn < below);
+}
+
+// One of edge e's three axes separates the widened cell with lower corner (x, y, z).
+GB_DEV bool edge_separates(const CullEdge& e, float x, float y, float z) {
+  const float cx = __fadd_rn(__fmul_rn(e.c[0][0], y), __fmul_rn(e.c[0][1], z));
+  const float cy = __fadd_rn(__fmul_rn(e.c[1][0], x), __fmul_rn(e.c[1][1], z));
+  const float cz = __fadd_rn(__fmul_rn(e.c[2][0], x), __fmul_rn(e.c[2][1], y));
+  return (cx > e.above[0]) | (cx < e.below[0]) | (cy > e.above[1]) | (cy < e.below[1]) | (cz > e.above[2]) |
+         (cz < e.below[2]);
 }
 
 // Grid coordinates of triangle t's vertices; true when the test applies (every
@@ -117,8 +135,49 @@ GB_DEV bool cull_grid_coords(const GridDev& G, uint32_t t, float u[3][3]) {
   return inside;
 }
 
+struct CullRecordArgs {
+  GridDev grid;
+  const uint64_t* box;      // [ntris] packed cell boxes of the count
+  CullRecord* rec;          // [ntris]
+  uint32_t ntris;
+  const Control* ctl;
+};
+
+// One thread per triangle (after the count, which has checked every vertex index).
+template <int Block>
+__global__ __launch_bounds__(Block) void cull_record_kernel(CullRecordArgs a) {
+  if (build_failed(a.ctl)) return;
+  const uint32_t stride = gridDim.x * Block;
+  for (uint32_t t = blockIdx.x * Block + threadIdx.x; t < a.ntris; t += stride) {
+    const Box b = unpack_box(a.box[t]);
+    float u[3][3];
+    const bool test = b.m[0] * b.m[1] * b.m[2] > 2u && cull_grid_coords(a.grid, t, u);
+    CullRecord& r = a.rec[t];
+    if (test) {
+      CullAxes ax;
+      cull_axes(u, ax);
+      r.n[0] = ax.n[0];
+      r.n[1] = ax.n[1];
+      r.n[2] = ax.n[2];
+      r.n_above = ax.n_above;
+      r.n_below = ax.n_below;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          r.e[i].c[j][0] = ax.e[3 * i + j][0];
+          r.e[i].c[j][1] = ax.e[3 * i + j][1];
+          r.e[i].above[j] = ax.e_above[3 * i + j];
+          r.e[i].below[j] = ax.e_below[3 * i + j];
+        }
+    }
+    r.test = test ? 1u : 0u;
+  }
+}
+
 struct CullArgs {
   ExpandOutArgs o;          // the expansion's arguments; cells/objs receive the kept pairs
+  const float4* rec;        // [ntris * 11] each triangle's CullRecord
   uint64_t dest_cap;        // entries cells/objs hold
   uint64_t* status;         // [expansion tiles] look-back words of the kept counts (zeroed)
 };
@@ -168,7 +227,6 @@ __global__ __launch_bounds__(Block, 4) void expand_cull_kernel(CullArgs a) {
     clear_status<Block>(a.o.clear, npairs);
     for (int i = threadIdx.x; i < 4 * R; i += Block) s_hist[i] = 0;
   }
-  const GridDev& G = a.o.ex.gs.one;
   const uint32_t tid = threadIdx.x;
   while (true) {
     const uint32_t tile = next_tile(&a.o.ctl->tile_counter[kCtrExpand], &s_tile);
@@ -176,27 +234,69 @@ __global__ __launch_bounds__(Block, 4) void expand_cull_kernel(CullArgs a) {
     uint32_t keys[K], vals[K], xyz[K];
     const uint32_t n =
         expand_tile<Block, K, false, kBlocked, true>(a.o.ex, tile, npairs, ntiles, s_owner, s_wtot, keys, vals, xyz);
-    // the overlap test, with the axes of the current object kept across its items
-    uint32_t keep = 0;
-    uint32_t cur = 0xFFFFFFFFu;
-    bool test = false;
-    CullAxes ax;
+    // the overlap test in four passes over the thread's items (the normal axis,
+    // then each edge's three axes), each loading only its part of the current
+    // object's record; an item is dropped when some axis separates it
+    uint32_t valid = 0, tested = 0, sep = 0;
+    {
+      uint32_t cur = 0xFFFFFFFFu;
+      bool test = false;
+      float nv[3] = {0.0f, 0.0f, 0.0f}, na = 0.0f, nb = 0.0f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (tid * K + k < n) {
-        if (vals[k] != cur) {
-          cur = vals[k];
-          const Box b = unpack_box(a.o.ex.box[cur]);
-          float u[3][3];
-          test = b.m[0] * b.m[1] * b.m[2] > 2u && cull_grid_coords(G, cur, u);
-          if (test) cull_axes(u, ax);
+      for (int k = 0; k < K; ++k) {
+        if (tid * K + k < n) {
+          valid |= 1u << k;
+          if (vals[k] != cur) {
+            cur = vals[k];
+            const float4 g0 = a.rec[static_cast<uint64_t>(cur) * kRecWords4];
+            const float4 g1 = a.rec[static_cast<uint64_t>(cur) * kRecWords4 + 1];
+            nv[0] = g0.x;
+            nv[1] = g0.y;
+            nv[2] = g0.z;
+            na = g0.w;
+            nb = g1.x;
+            test = __float_as_uint(g1.y) != 0u;
+          }
+          if (test) {
+            tested |= 1u << k;
+            if (normal_separates(nv, na, nb, static_cast<float>(xyz[k] & 1023u),
+                                 static_cast<float>((xyz[k] >> 10) & 1023u), static_cast<float>(xyz[k] >> 20)))
+              sep |= 1u << k;
+          }
         }
-        const float x = static_cast<float>(xyz[k] & 1023u);
-        const float y = static_cast<float>((xyz[k] >> 10) & 1023u);
-        const float z = static_cast<float>(xyz[k] >> 20);
-        if (!test || cull_touches(ax, x, y, z)) keep |= 1u << k;
       }
     }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      uint32_t cur = 0xFFFFFFFFu;
+      CullEdge e{};
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if ((tested >> k) & 1u) {
+          if (vals[k] != cur) {
+            cur = vals[k];
+            const float4* g = a.rec + static_cast<uint64_t>(cur) * kRecWords4 + 2 + 3 * i;
+            const float4 g0 = g[0], g1 = g[1], g2 = g[2];
+            e.c[0][0] = g0.x;
+            e.c[0][1] = g0.y;
+            e.c[1][0] = g0.z;
+            e.c[1][1] = g0.w;
+            e.c[2][0] = g1.x;
+            e.c[2][1] = g1.y;
+            e.above[0] = g1.z;
+            e.above[1] = g1.w;
+            e.above[2] = g2.x;
+            e.below[0] = g2.y;
+            e.below[1] = g2.z;
+            e.below[2] = g2.w;
+          }
+          if (edge_separates(e, static_cast<float>(xyz[k] & 1023u), static_cast<float>((xyz[k] >> 10) & 1023u),
+                             static_cast<float>(xyz[k] >> 20)))
+            sep |= 1u << k;
+        }
+      }
+    }
+    const uint32_t keep = valid & ~sep;
     // rank of each kept item among all kept items: thread, then tile, then look-back
     uint32_t ttot;
     const uint32_t texcl = block_exclusive_sum<Block>(static_cast<uint32_t>(__builtin_popcount(keep)), s_wtot, ttot);

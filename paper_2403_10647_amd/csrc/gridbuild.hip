@@ -185,13 +185,13 @@ uint32_t tfo_work_cap(uint32_t ntfo) { return ntfo / kTfoInline + 2; }
 
 struct Layout {
   size_t ctl, hist, count_status, cull_status, cell_status, zero_end;
-  size_t start, box, tfo, tfg, tfo_work, sort_status, keys_alt, vals_alt, keys_alt2, vals_alt2, run, npairs_out, splits,
+  size_t start, box, tfo, tfg, tfo_work, cull_rec, sort_status, keys_alt, vals_alt, keys_alt2, vals_alt2, run, npairs_out, splits,
       tile_grid, table, sink, kmap, ksink, total;
   uint32_t ntfo, ncount_tiles, nsort_tiles_cap, nmerge_tiles_cap;
 };
 
 Layout make_layout(uint64_t ntris, uint64_t cap_pairs, uint64_t ncells_plus_grids, const Plan& plan,
-                   uint32_t ngrids, bool batched) {
+                   uint32_t ngrids, bool batched, bool culled = false) {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -214,6 +214,7 @@ Layout make_layout(uint64_t ntris, uint64_t cap_pairs, uint64_t ncells_plus_grid
   L.tfo = take(static_cast<size_t>(L.ntfo) * 4);
   L.tfg = take(batched ? static_cast<size_t>(L.ntfo) * 4 : 0);
   L.tfo_work = take(tfo_work_cap(L.ntfo) * sizeof(uint4));
+  L.cull_rec = take(culled ? ntris * sizeof(CullRecord) : 0);  // culled builds: each triangle's test
   L.sort_status = take(static_cast<size_t>(plan.sp.passes) * L.nsort_tiles_cap * (size_t{1} << plan.rb) * 8);
   L.keys_alt = take(cap_pairs * 4);
   L.vals_alt = take(cap_pairs * 4);
@@ -525,7 +526,20 @@ template <int RB>
 int launch_cull(Build& b, uint32_t* cells, uint32_t* objs, uint64_t dest_cap, uint64_t box_cap) {
   if (box_cap > 0) {
     if (!cells || !objs) return GRID_E_INVAL;
+    CullRecordArgs r{};
+    r.grid = b.gs.one;
+    r.box = at<uint64_t>(b.ws, b.L.box);
+    r.rec = at<CullRecord>(b.ws, b.L.cull_rec);
+    r.ntris = b.ntris;
+    r.ctl = at<Control>(b.ws, b.L.ctl);
+    if (b.ntris > 0) {
+      TraceScope tr(b.s, "cull_record");
+      cull_record_kernel<256><<<static_cast<uint32_t>(std::min<uint64_t>(ceil_div(b.ntris, 256), 8192)), 256, 0,
+                                b.s>>>(r);
+      GB_LAUNCHED();
+    }
     CullArgs a{};
+    a.rec = reinterpret_cast<const float4*>(r.rec);
     a.o.ex = expand_args(b);
     a.o.cells = cells;
     a.o.objs = objs;
@@ -788,7 +802,7 @@ int read_ctl(const Build& b, HostCtl* h) {
 
 int prepare_plain(Build& b, const float* verts, uint32_t nverts, const uint32_t* tris, uint32_t ntris,
                   const float lo[3], const float hi[3], const uint32_t res[3], void* ws, size_t ws_bytes,
-                  uint64_t cap_pairs, hipStream_t s) {
+                  uint64_t cap_pairs, hipStream_t s, bool culled = false) {
   int st = check_grid(lo, hi, res);
   if (st != GRID_OK) return st;
   if (!ws) return GRID_E_INVAL;
@@ -799,7 +813,7 @@ int prepare_plain(Build& b, const float* verts, uint32_t nverts, const uint32_t*
   b.ntris = ntris;
   b.batched = false;
   b.plan = make_plan(bits_for(ncells_of(res)));
-  b.L = make_layout(ntris, cap_pairs, ncells_of(res) + 1, b.plan, 1, false);
+  b.L = make_layout(ntris, cap_pairs, ncells_of(res) + 1, b.plan, 1, false, culled);
   if (ws_bytes < b.L.total) return GRID_E_NOMEM;
   b.gs = GridSet{};
   b.gs.one = make_grid(verts, nverts, tris, ntris, lo, hi, res);
@@ -840,6 +854,12 @@ size_t grid_workspace_size(uint32_t ntris, uint64_t cap_pairs, const uint32_t re
   if (!res) return 0;
   const uint64_t nc = ncells_of(res);
   return make_layout(ntris, cap_pairs, nc + 1, make_plan(bits_for(nc)), 1, false).total;
+}
+
+size_t grid_workspace_size_culled(uint32_t ntris, uint64_t box_cap, const uint32_t res[3]) {
+  if (!res) return 0;
+  const uint64_t nc = ncells_of(res);
+  return make_layout(ntris, box_cap, nc + 1, make_plan(bits_for(nc)), 1, false, true).total;
 }
 
 int grid_count(const float* verts_soa, uint32_t nverts, const uint32_t* tris, uint32_t ntris, const float lo[3],
@@ -911,7 +931,7 @@ int grid_build_culled(const float* verts_soa, uint32_t nverts, const uint32_t* t
   Build b{};
   // the layout (expansion tiles, workspace pair buffers) is sized for the box pairs
   int st = prepare_plain(b, verts_soa, nverts, tris, ntris, lo, hi, res, ws, ws_bytes, box_cap,
-                         static_cast<hipStream_t>(stream));
+                         static_cast<hipStream_t>(stream), true);
   if (st) return st;
   b.culled = true;
   b.out_cap = out->cap_pairs;

@@ -55,6 +55,10 @@ def test_workspace_sizes_grow(G):
     c = G.workspace_size(100000, 400000, [32, 32, 32])
     assert 0 < a < b < c
     L = G.lib()
+    # culled builds add one 176-byte test record per triangle
+    assert G.workspace_size_culled(1000, 4000, [32, 32, 32]) >= a + 176 * 1000 - 256   # one empty region fewer
+    assert G.workspace_size_culled(100000, 400000, [32, 32, 32]) >= c + 176 * 100000 - 256
+    assert L.grid_workspace_size_culled(10, 10, None) == 0
     assert L.grid_sort_workspace_size(1 << 20, 25) > L.grid_sort_workspace_size(1 << 20, 8) > 0
     assert L.grid_sort_workspace_size(10, 33) == 0
     assert L.grid_scan_workspace_size(1 << 20) > L.grid_scan_workspace_size(10) > 0

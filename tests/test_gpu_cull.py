@@ -130,7 +130,7 @@ def test_culled_capacity_errors(G):
     # a box capacity below the box pairs: nothing is kept, the box count is reported
     L = G.lib()
     ws = G.Workspace()
-    wp, wn = ws.ptr_size(G.workspace_size(g.ntris, nbox - 1, g.res))
+    wp, wn = ws.ptr_size(G.workspace_size_culled(g.ntris, nbox - 1, g.res))
     big = torch.zeros(nbox, dtype=torch.int32, device="cuda")
     o = G.grid_out(big.data_ptr(), big.data_ptr(), out.ranges.data_ptr(), nbox, 0)
     nb = C.c_uint64(0)
