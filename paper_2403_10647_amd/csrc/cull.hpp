@@ -211,7 +211,7 @@ GB_DEV void hist_runs_kept(const SortPlan& plan, const uint32_t (&keys)[K], uint
 // kept pairs; with RB > 0 also the kept keys' digit histograms and the radix
 // passes' cleared look-back words.  The last tile writes the kept total.
 template <int Block, int K, int RB>
-__global__ __launch_bounds__(Block, 4) void expand_cull_kernel(CullArgs a) {
+__global__ __launch_bounds__(Block, 6) void expand_cull_kernel(CullArgs a) {
   constexpr int N = Block * K;
   constexpr int R = RB > 0 ? 1 << RB : 1;
   static_assert(K <= 32, "a thread's keep flags fit one word");
