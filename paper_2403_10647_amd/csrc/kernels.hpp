@@ -624,7 +624,7 @@ GB_DEV void flush_hist(const SortPlan& plan, uint32_t* hist, const uint32_t* s_h
 // builds skip the tiles that straddle grids here; expand_straddle_kernel
 // writes those.
 template <int Block, int K, int RB, bool Batched>
-__global__ __launch_bounds__(Block, 4) void expand_kernel(ExpandOutArgs a) {
+__global__ __launch_bounds__(Block, 6) void expand_kernel(ExpandOutArgs a) {
   constexpr int N = Block * K;
   constexpr int R = RB > 0 ? 1 << RB : 1;
   static_assert(K % 4 == 0, "items are stored four at a time");
