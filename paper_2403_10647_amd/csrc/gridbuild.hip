@@ -103,13 +103,16 @@ Tracer& tracer() {
   return t;
 }
 
+// A span scope brackets several launches (a build's radix passes) and is
+// recorded only when selected by name, so that it never overlaps the
+// per-kernel totals of a full trace.
 class TraceScope {
  public:
-  TraceScope(hipStream_t s, const char* name) : s_(s) {
+  TraceScope(hipStream_t s, const char* name, bool span = false) : s_(s) {
     Tracer& t = tracer();
     if (!t.on) return;
     std::lock_guard<std::mutex> lock(t.mu);
-    if (t.only[0] && std::strncmp(t.only, name, sizeof(t.only)) != 0) return;
+    if ((t.only[0] || span) && std::strncmp(t.only, name, sizeof(t.only)) != 0) return;
     rec_.name = name;
     rec_.a = t.get();
     rec_.b = t.get();
@@ -694,41 +697,44 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
     in_k = d.k;
     in_v = d.v;
   }
-  for (uint32_t p = 0; p < P; ++p) {
-    const Dest d = sort_dest(b, B, static_cast<int>(p), P, out_cells, out_objs);
-    const bool last = p + 1 == P;
-    if ((!B || !last) && (!d.k || !d.v)) return GRID_E_INVAL;  // never launch a pass without a destination
-    SortPassArgs a{};
-    a.keys_in = in_k;
-    a.vals_in = in_v;
-    a.keys_out = d.k;
-    a.vals_out = d.v;
-    a.ex = expand_args(b);
-    a.hist = at<uint32_t>(b.ws, b.L.hist) + p * kRadixMax;
-    a.hist_copies = kHistCopies;
-    a.hist_stride = 4 * kRadixMax;
-    a.status = at<uint64_t>(b.ws, b.L.sort_status) + static_cast<uint64_t>(p) * b.L.nsort_tiles_cap * (1u << RB);
-    a.n = npairs;
-    a.n_from_ctl = 1;  // the pass reads NO from the control block
-    a.shift = sp.shift[p];
-    a.width = sp.width[p];
-    a.counter = kCtrSort0 + p;
-    a.sink = at<GridSink>(b.ws, b.L.sink);
-    a.kmap = at<uint2>(b.ws, b.L.kmap);
-    a.ksink = at<GridSink>(b.ws, b.L.ksink);
-    {
-      const uint32_t kbits = bits_for(b.batch_cells);
-      a.kshift = kbits > static_cast<uint32_t>(kKeyMapBits) ? kbits - kKeyMapBits : 0;
+  {
+    TraceScope span(b.s, "radix_passes", true);  // all of the build's passes, between two events
+    for (uint32_t p = 0; p < P; ++p) {
+      const Dest d = sort_dest(b, B, static_cast<int>(p), P, out_cells, out_objs);
+      const bool last = p + 1 == P;
+      if ((!B || !last) && (!d.k || !d.v)) return GRID_E_INVAL;  // never launch a pass without a destination
+      SortPassArgs a{};
+      a.keys_in = in_k;
+      a.vals_in = in_v;
+      a.keys_out = d.k;
+      a.vals_out = d.v;
+      a.ex = expand_args(b);
+      a.hist = at<uint32_t>(b.ws, b.L.hist) + p * kRadixMax;
+      a.hist_copies = kHistCopies;
+      a.hist_stride = 4 * kRadixMax;
+      a.status = at<uint64_t>(b.ws, b.L.sort_status) + static_cast<uint64_t>(p) * b.L.nsort_tiles_cap * (1u << RB);
+      a.n = npairs;
+      a.n_from_ctl = 1;  // the pass reads NO from the control block
+      a.shift = sp.shift[p];
+      a.width = sp.width[p];
+      a.counter = kCtrSort0 + p;
+      a.sink = at<GridSink>(b.ws, b.L.sink);
+      a.kmap = at<uint2>(b.ws, b.L.kmap);
+      a.ksink = at<GridSink>(b.ws, b.L.ksink);
+      {
+        const uint32_t kbits = bits_for(b.batch_cells);
+        a.kshift = kbits > static_cast<uint32_t>(kKeyMapBits) ? kbits - kKeyMapBits : 0;
+      }
+      a.ctl = ctl;
+      const bool regen = fused && p == 0;
+      const uint32_t pass_tiles = static_cast<uint32_t>(ceil_div(npairs, pass_tile(b, p)));
+      TraceScope ts(b.s, regen ? "onesweep_expand" : (B && last) ? "onesweep_grids" : "onesweep");
+      int st = launch_pass<B>(a, pass_bits(sp.width[p]), regen, B && last, pass_tiles, b.s);
+      if (st) return st;
+      GB_LAUNCHED();
+      in_k = d.k;
+      in_v = d.v;
     }
-    a.ctl = ctl;
-    const bool regen = fused && p == 0;
-    const uint32_t pass_tiles = static_cast<uint32_t>(ceil_div(npairs, pass_tile(b, p)));
-    TraceScope ts(b.s, regen ? "onesweep_expand" : (B && last) ? "onesweep_grids" : "onesweep");
-    int st = launch_pass<B>(a, pass_bits(sp.width[p]), regen, B && last, pass_tiles, b.s);
-    if (st) return st;
-    GB_LAUNCHED();
-    in_k = d.k;
-    in_v = d.v;
   }
   return GRID_OK;
 }
