@@ -81,6 +81,42 @@ def _set(G, knobs: Dict[str, int]) -> None:
         G.tune_set(k, int(knobs[k]))
 
 
+def set_knobs(G, knobs: Dict[str, int]) -> None:
+    """Set every tuned knob (a setting from tune_plain, tune_batched or DEFAULTS)."""
+    _set(G, knobs)
+
+
+def confirm_plain(g, best: Dict[str, int], rounds: int = 3, reps: int = 10, G=None) -> Tuple[Dict[str, int], dict]:
+    """Time ``best`` against the defaults in alternating rounds on plain builds of ``g``
+    and keep the faster by median; returns (knobs, medians in ms)."""
+    import statistics
+    import torch
+    if G is None:
+        from . import _lib as G
+    ws = G.Workspace()
+    npairs, _ = G.count(g, ws)
+    ws.get(max_workspace(G, g, npairs))
+    out = G.build(g, cap_pairs=npairs, ws=ws)
+    run = G.PlainBuild(g, out, ws)
+    old = {k: G.tune_get(k) for k in KNOBS}
+    times = {"default": [], "tuned": []}
+    try:
+        for _ in range(rounds):
+            for name, knobs in (("default", DEFAULTS), ("tuned", best)):
+                _set(G, knobs)
+                run()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    run()
+                torch.cuda.synchronize()
+                times[name].append((time.perf_counter() - t0) * 1e3 / reps)
+    finally:
+        _set(G, old)
+    med = {k: round(statistics.median(v), 5) for k, v in times.items()}
+    return (dict(best) if med["tuned"] < med["default"] else dict(DEFAULTS)), med
+
+
 def _device_name() -> str:
     import torch
     return torch.cuda.get_device_name(0)

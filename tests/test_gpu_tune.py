@@ -62,3 +62,24 @@ def test_tune_plain_wide_key(G, tmp_path):
     c, o, r = G.build(g).numpy()
     oc, oo, orr = oracle.build_scene(s)
     assert np.array_equal(c, oc) and np.array_equal(o, oo) and np.array_equal(r, orr)
+
+
+def test_confirm_plain_keeps_the_faster_and_restores_knobs(G):
+    # the bench confirms the search's best against the defaults before timing
+    # the headline build with it; a 22-bit key sizes the workspace for 11-bit digits
+    base = scenes.make_scene("mixed", seed=11, ntris=30_000)
+    s = scenes.Scene("mixed22", base.verts, base.tris, base.lo, base.hi, np.array([160, 160, 160], np.uint32))
+    g = G.GridInput.from_scene(s)
+    cand = {"max_digit_bits": 11, "sort_shape": 0, "fused_expand": 0}
+    chosen, med = tune.confirm_plain(g, cand, rounds=2, reps=2, G=G)
+    assert chosen in (cand, tune.DEFAULTS)
+    assert set(med) == {"default", "tuned"} and all(v > 0 for v in med.values())
+    assert chosen == (cand if med["tuned"] < med["default"] else tune.DEFAULTS)
+    assert all(G.tune_get(k) == v for k, v in tune.DEFAULTS.items())
+    try:
+        tune.set_knobs(G, chosen)
+        c, o, r = G.build(g).numpy()
+        oc, oo, orr = oracle.build_scene(s)
+        assert np.array_equal(c, oc) and np.array_equal(o, oo) and np.array_equal(r, orr)
+    finally:
+        tune.set_knobs(G, tune.DEFAULTS)
