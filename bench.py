@@ -71,15 +71,20 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if it is current."""
+def knobs_key(knobs: dict) -> str:
+    return ",".join(f"{k}={int(knobs[k])}" for k in ("max_digit_bits", "sort_shape", "fused_expand"))
+
+
+def load_traffic(kernel: str, workload: str, knobs: dict):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken at
+    these knobs and is current."""
     path = os.path.join(PROFILES, "traffic.json")
     try:
         with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    e = d.get(workload, {}).get(kernel)
+    e = d.get(workload, {}).get(knobs_key(knobs), {}).get(kernel)
     if not e or e.get("source_hash") != source_hash():
         return None
     return e.get("hbm_bytes_per_launch")
@@ -670,7 +675,7 @@ def main():
         avg_ms = tot_ms / launches
         bpl = kernel_bytes(dom, T, NO, R)
         achieved = bpl / (avg_ms * 1e-3) / 1e9
-        traffic = load_traffic(dom, args.workload)
+        traffic = load_traffic(dom, args.workload, knobs)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                     "avg_launch_ms": round(avg_ms, 5), "bytes_per_launch": int(bpl),
