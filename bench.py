@@ -48,7 +48,7 @@ def kernel_bytes(name: str, T: int, NO: int, R: int) -> float:
 
 
 def survey_bytes(T: int, NO: int, R: int, passes: int) -> int:
-    """The survey's per-build byte model at the radix passes the build runs:
+    """The unfused per-build byte model, at the radix passes the build runs:
     80 T + (16 + 16 P) NO + 8 R (inputs, count/start and box round trips, the
     expansion's pairs, one histogram read, P passes that read and write key and
     value, the range pass's read of the sorted cells, and the range table)."""
@@ -155,7 +155,7 @@ def run_copy(steps: int):
 def run_configs(G, args, steps: int = 20) -> dict:
     """The other single-grid configurations: the 4096-triangle scene (launch
     bound: microseconds per build) and the 1M mixed scene (ms per build,
-    Mpairs/s, the dominant kernel's roofline and the survey model's fraction)."""
+    Mpairs/s, the dominant kernel's roofline and the unfused byte model's fraction)."""
     import torch
     from paper_2403_10647_amd import scenes
     res = {}
