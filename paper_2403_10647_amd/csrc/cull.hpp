@@ -210,6 +210,9 @@ GB_DEV void hist_runs_kept(const SortPlan& plan, const uint32_t (&keys)[K], uint
 // tested and the kept ones written, in object order, at their rank among all
 // kept pairs; with RB > 0 also the kept keys' digit histograms and the radix
 // passes' cleared look-back words.  The last tile writes the kept total.
+// Six waves per SIMD (80 VGPRs; three values spill, reloaded once per tile,
+// outside the test) measured fastest: five waves without spills, or eight
+// with many, were slower.
 template <int Block, int K, int RB>
 __global__ __launch_bounds__(Block, 6) void expand_cull_kernel(CullArgs a) {
   constexpr int N = Block * K;

@@ -622,7 +622,9 @@ GB_DEV void flush_hist(const SortPlan& plan, uint32_t* hist, const uint32_t* s_h
 // The expansion written out in object order, with the digit histograms of
 // every radix pass and the look-back words of every pass cleared.  Batched
 // builds skip the tiles that straddle grids here; expand_straddle_kernel
-// writes those.
+// writes those.  Bounded to six waves per SIMD (at most 80 VGPRs, no spills):
+// at five, the owners' dependent loads were hidden less well (0.186 against
+// 0.167 ms on 51M pairs).
 template <int Block, int K, int RB, bool Batched>
 __global__ __launch_bounds__(Block, 6) void expand_kernel(ExpandOutArgs a) {
   constexpr int N = Block * K;
