@@ -132,3 +132,29 @@ def test_bad_request_fails_alone(G, workload):
     assert st.failed == 1 and st.completed == len(reqs) - 1
     assert reqs[-1].status == G.GRID_E_BADINDEX
     _check_alone(G, reqs[:-1], refs)
+
+
+def test_empty_and_one_cell_requests(G, workload):
+    # requests with no triangles and a one-cell grid go through the count and
+    # the resumed build like any other, alone and mixed with the others
+    from paper_2403_10647_amd import serve
+    _, _, pool, big, refs = workload
+    empty = G.GridInput(torch.zeros((3, 0), dtype=torch.float32, device="cuda"),
+                        torch.zeros((0, 3), dtype=torch.int32, device="cuda"), [0.0, 0.0, 0.0], [1.0, 1.0, 1.0], [3, 2, 5])
+    g0 = pool[2]
+    one = G.GridInput(g0.verts, g0.tris, g0.lo, g0.hi, [1, 1, 1])
+    extra = [empty, one]
+    extra_refs = [G.build(g) for g in extra]
+    torch.cuda.synchronize()
+    pool2 = list(pool) + extra
+    refs2 = list(refs[:-1]) + extra_refs
+    reqs = serve.make_requests(pool2, rate=4000.0, duration=0.05, seed=12, burst=False)
+    n0 = len(reqs)
+    reqs += [serve.Request(n0 + i, 0.001 * i, g, len(pool) + (i % 2)) for i, g in enumerate(extra * 3)]
+    ws = serve.batch_workspace_bytes(pool, [r.npairs for r in refs[:-1]])
+    srv = serve.Server(8 * ws, ws, nslots=2, max_pairs=1 << 20, references=refs2, keep_results=True)
+    st = srv.run(reqs)
+    _say(st.as_dict())
+    assert st.completed == len(reqs) and st.mismatches == 0
+    assert extra_refs[0].npairs == 0 and extra_refs[1].npairs == one.ntris
+    _check_alone(G, reqs, refs2)
