@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgridbuild.so")
 SOURCES = ["gridbuild.hip"]
-HEADERS = ["common.hpp", "grid.hpp", "kernels.hpp", "sort.hpp", "ranges.hpp", "scan.hpp", "cull.hpp"]
+HEADERS = ["common.hpp", "grid.hpp", "tiles.hpp", "kernels.hpp", "sort.hpp", "ranges.hpp", "scan.hpp", "cull.hpp",
+           "compact.hpp", "raycast.hpp"]
 ARCH = os.environ.get("GRIDBUILD_ARCH", "gfx950")
 
 FLAGS = [

@@ -182,9 +182,7 @@ Plan make_plan(uint32_t bits, int max_digit = -1) {
 }
 
 // ---- workspace layout -----------------------------------------------------------
-// Tile-owner runs the count can leave to the plan kernel: each run is more
-// than kTfoInline entries of the table.
-uint32_t tfo_work_cap(uint32_t ntfo) { return ntfo / kTfoInline + 2; }
+// (tfo_work_cap, the tile-owner runs the count can leave to the plan kernel, is in tiles.hpp)
 
 struct Layout {
   size_t ctl, hist, count_status, cull_status, cell_status, zero_end;

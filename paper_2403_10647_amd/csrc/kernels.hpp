@@ -5,6 +5,7 @@
 
 #include "common.hpp"
 #include "grid.hpp"
+#include "tiles.hpp"
 
 namespace gb {
 
@@ -80,10 +81,6 @@ struct CountArgs {
   Control* ctl;
 };
 
-// Tile-owner entries the count writes per object; an object that owns the
-// first pair of more expansion tiles leaves the rest to the plan kernel, whose
-// whole workgroup writes them, so no thread writes more than this many.
-constexpr uint32_t kTfoInline = 32;
 
 // Grid of triangle t (largest g with tri_base[g] <= t), found by one whole
 // wave: each level probes 64 evenly spaced grids of the remaining range at
@@ -223,29 +220,26 @@ __global__ __launch_bounds__(Block) void count_kernel(CountArgs a) {
   __syncthreads();
   excl += s_prefix;
 
-  const uint64_t tmask = (uint64_t{1} << a.tile_shift) - 1;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const uint64_t t = base + static_cast<uint64_t>(tid) * K + k;
     s_val[pad32(tid * K + k)] = static_cast<uint32_t>(excl);
     if (mine[k] != 0 && t < a.ntris) {
       // expansion tiles whose first pair this object owns
-      uint64_t j = (excl + tmask) >> a.tile_shift;
-      const uint64_t jlast = (excl + mine[k] - 1) >> a.tile_shift;
-      if (j <= jlast && j < a.ntfo) {
+      const OwnedTiles ot = owned_tiles(excl, mine[k], a.tile_shift, a.ntfo);
+      if (ot.any) {
         // about one object per expansion tile; its grid is the tile's first
         // or one a few entries after it
         const uint32_t g = one ? gl : grid_of_tri<Batched>(a.gs, static_cast<uint32_t>(t), gl);
-        const uint64_t jend = jlast < a.ntfo ? jlast : a.ntfo - 1;
-        const uint64_t jin = j + kTfoInline - 1 < jend ? j + kTfoInline - 1 : jend;
-        for (; j <= jin; ++j) {
+        for (uint64_t j = ot.lo; j <= ot.inl; ++j) {
           a.tfo[j] = static_cast<uint32_t>(t);
           if constexpr (Batched) a.tfg[j] = g;
         }
-        if (j <= jend) {  // a huge object: the rest of its run goes to the plan kernel
+        if (ot.inl < ot.hi) {  // a huge object: the rest of its run goes to the plan kernel
           const uint32_t w = atomicAdd(&a.ctl->tfo_work_n, 1u);
           if (w < a.tfo_work_cap)
-            a.tfo_work[w] = make_uint4(static_cast<uint32_t>(t), g, static_cast<uint32_t>(j), static_cast<uint32_t>(jend));
+            a.tfo_work[w] = make_uint4(static_cast<uint32_t>(t), g, static_cast<uint32_t>(ot.inl + 1),
+                                       static_cast<uint32_t>(ot.hi));
           else
             atomicOr(&a.ctl->error, kErrInternal);
         }

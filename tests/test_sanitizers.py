@@ -1,7 +1,9 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer (no GPU):
-the CPU oracle (tests/sanitize/check_oracle.c linked with oracle/oracle.cpp)
-and the library's host-side logic (tests/sanitize/check_abi_host.cpp built with
-the library's source, sanitizers on the host side only).  Each program exits 0
+the CPU oracle (tests/sanitize/check_oracle.c linked with oracle/oracle.cpp),
+the library's host-side logic (tests/sanitize/check_abi_host.cpp built with
+the library's source, sanitizers on the host side only), and the tile-owner
+index logic the count kernel runs, checked on the host against brute force
+(tests/sanitize/check_tile_owners.cpp).  Each program exits 0
 when its checks pass and the sanitizers report nothing."""
 import os
 import shutil
@@ -47,5 +49,17 @@ def test_library_host_code_under_asan_ubsan():
            "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
            "-Xarch_host", "-fno-sanitize-recover=all",
            f"-I{os.path.join(ROOT, 'include')}", src, os.path.join(SAN, "check_abi_host.cpp"), "-o", exe]
+    subprocess.check_call(cmd, stderr=subprocess.DEVNULL)
+    _run(exe)
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC), reason="no hipcc")
+def test_tile_owner_index_logic_on_the_host():
+    os.makedirs(OUT, exist_ok=True)
+    exe = os.path.join(OUT, "check_tile_owners")
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=all",
+           f"-I{os.path.join(ROOT, 'paper_2403_10647_amd', 'csrc')}", os.path.join(SAN, "check_tile_owners.cpp"), "-o", exe]
     subprocess.check_call(cmd, stderr=subprocess.DEVNULL)
     _run(exe)
