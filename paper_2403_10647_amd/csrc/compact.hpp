@@ -48,8 +48,7 @@ __global__ __launch_bounds__(Block, 4) void compact_count_kernel(CompactArgs a) 
     if (tile >= ntiles) break;
     uint32_t keys[K], vals[K];
     const uint32_t n = expand_tile<Block, K, false, kBlocked, true>(a.ex, tile, npairs, ntiles, s_owner, s_wtot, keys, vals);
-#pragma unroll
-    for (int k = 0; k < K; ++k)
+    for (int k = 0; k < K; ++k)  // unrolled by the compiler (constant trip count)
       if (threadIdx.x * K + k < n) atomicAdd(&a.ranges[2 * static_cast<uint64_t>(keys[k]) + 1], 1u);
   }
 }

@@ -34,10 +34,19 @@ struct SortPassArgs {
   Control* ctl;
 };
 
-// Two workgroups per CU when the keys come from arrays (at most 128 VGPRs);
-// the regenerating variant needs more registers and runs one per CU.
+// Waves per SIMD asked of the register allocator: four (at most 128 VGPRs)
+// when the keys come from arrays, except for the 16-key shapes with the widest
+// digits, whose rank needs more registers (three waves at 256 threads, two at
+// 512 with 11-bit digits); the regenerating variant runs two.
+constexpr int onesweep_waves(int Block, int K, int RB, int Source) {
+  return Source != kFromArrays ? 2
+         : (Block == 256 && K == 16 && RB >= 10) ? 3
+         : (Block == 512 && K == 16 && RB >= 11) ? 2
+         : 4;
+}
+
 template <int Block, int K, int RB, int Source, int Sink, bool Batched>
-__global__ __launch_bounds__(Block, Source == kFromArrays ? 4 : 2) void onesweep_kernel(SortPassArgs a) {
+__global__ __launch_bounds__(Block, onesweep_waves(Block, K, RB, Source)) void onesweep_kernel(SortPassArgs a) {
   constexpr int N = Block * K;
   constexpr int R = 1 << RB;
   constexpr int W = Block / kWave;
