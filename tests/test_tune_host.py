@@ -1,8 +1,6 @@
 """Host logic of the autotuner: candidates, signatures and the cache file."""
 import json
 
-import pytest
-
 from paper_2403_10647_amd import tune
 
 
