@@ -132,11 +132,22 @@ GB_DEV void count_items(const CountArgs& a, const GridDev& G0, uint64_t base, ui
   for (int k = 0; k < K; ++k) {
     const GridDev& G = Mode == kCountPerItem ? a.gs.table[gi[k]] : G0;
     bad[k] = idx[k][0] >= G.nverts || idx[k][1] >= G.nverts || idx[k][2] >= G.nverts;
+    // a triangle of a soup lists three consecutive vertices: each coordinate's
+    // three values are then one 12-byte load instead of three (plain builds; the
+    // batched count has no registers to spare for it)
+    const bool seq = Mode == kCountPlain && !bad[k] && idx[k][1] == idx[k][0] + 1u && idx[k][2] == idx[k][0] + 2u;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const float* v = G.verts + static_cast<uint64_t>(ax) * G.nverts;
+      if (seq) {
+        const float3 q = *reinterpret_cast<const float3*>(v + idx[k][0]);
+        p[k][ax][0] = q.x;
+        p[k][ax][1] = q.y;
+        p[k][ax][2] = q.z;
+      } else {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) p[k][ax][c] = bad[k] ? 0.0f : v[idx[k][c]];  // no load for a bad index
+        for (int c = 0; c < 3; ++c) p[k][ax][c] = bad[k] ? 0.0f : v[idx[k][c]];  // no load for a bad index
+      }
     }
   }
 #pragma unroll

@@ -220,6 +220,21 @@ def test_build_indexed_mesh(G):
     _check_build(G, _scene(verts, tris, [0, 0, 0], [10, 10, 10], [20, 20, 20], "indexed"))
 
 
+def test_build_soup_and_indexed_triangles_interleaved(G):
+    # triangles listing three consecutive vertices (one wide load per
+    # coordinate in the count) side by side with ones that list their own three
+    # vertices in another order or repeat one (three loads), within the same waves
+    rng = np.random.default_rng(17)
+    n = 20_000
+    centres = rng.uniform(0.5, 9.5, size=(n, 3))
+    verts = np.ascontiguousarray((centres.repeat(3, axis=0) + rng.uniform(-0.2, 0.2, size=(3 * n, 3))).T, np.float32)
+    base = 3 * np.arange(n, dtype=np.uint32)[:, None]
+    orders = np.array([[0, 1, 2], [1, 0, 2], [2, 1, 0], [0, 2, 1], [0, 0, 1], [2, 2, 2]], np.uint32)
+    pick = np.where(rng.random(n) < 0.5, 0, rng.integers(1, len(orders), size=n))
+    tris = np.ascontiguousarray(base + orders[pick], np.uint32)
+    _check_build(G, _scene(verts, tris, [0, 0, 0], [10, 10, 10], [40, 40, 40], "soup+reordered"))
+
+
 def test_repeat_builds_identical(G):
     s = scenes.make_scene("arch", ntris=100_000)
     g = G.GridInput.from_scene(s)
