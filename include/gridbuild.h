@@ -18,7 +18,10 @@
  *    whose required size the *_workspace_size functions report.
  *  - stream is a hipStream_t (NULL = the default stream).  All device work is
  *    ordered on it.  Entry points that must read a result back (the pair count)
- *    synchronize that stream once and say so.
+ *    synchronize that stream once and say so.  Their readback lands in one small
+ *    pinned host block per calling host thread, allocated on that thread's first
+ *    such call and kept until the process ends (grid_build_static excepted: it
+ *    reads back through pageable memory and allocates nothing).
  *  - Inputs: verts_soa is FP32 [3][nverts] (all x, then all y, then all z);
  *    tris is uint32 [ntris][3] vertex indices.  lo, hi (host, 3 floats) are the
  *    grid bounds and res (host, 3 uint32) the cells per axis.

@@ -167,14 +167,17 @@ Plan make_plan(uint32_t bits, int max_digit = -1) {
   // at most 4 passes (the plan's arrays and the histogram slots): a narrow
   // digit limit on a wide key widens the digits instead (32 bits / 4 = 8)
   const uint32_t passes = std::min<uint32_t>(4, (bits + md - 1) / md);
-  // widths as even as possible (25 bits: 9, 8, 8): a wider digit costs its
-  // pass more counters, look-back words and shorter scatter runs
+  // widths as even as possible: a wider digit costs its pass more counters,
+  // look-back words and shorter scatter runs.  The wider digits are the top
+  // ones (25 bits: 8, 8, 9): keys below a cell count that is not a power of
+  // two take fewer values in the top digit than its width allows, so the
+  // wide pass gets longer runs than it would on the low digit
   const uint32_t base = bits / passes, extra = bits % passes;
   p.sp.passes = passes;
   uint32_t shift = 0;
   for (uint32_t i = 0; i < passes; ++i) {
     p.sp.shift[i] = shift;
-    p.sp.width[i] = base + (i < extra ? 1u : 0u);
+    p.sp.width[i] = base + (i >= passes - extra ? 1u : 0u);
     shift += p.sp.width[i];
   }
   p.rb = std::max(8, static_cast<int>(base + (extra ? 1u : 0u)));
@@ -304,6 +307,7 @@ struct Build {
   bool culled;           // plain builds: false intersections removed before the sort
   uint64_t out_cap;      // culled builds: pairs the caller's outputs hold
   uint64_t layout_cap = ~uint64_t{0};  // pairs the workspace layout holds, checked by the plan
+  bool no_alloc = false;  // the build may not allocate, not even host memory for its readback
 };
 
 template <bool B>
@@ -793,14 +797,34 @@ int device_error(uint32_t error) {
   return GRID_OK;
 }
 
+// Host end of the control block's readback: one pinned block per host thread,
+// allocated by that thread's first synchronous build and kept until the
+// process ends.  A copy into pinned memory is one DMA; a copy into pageable
+// memory goes through the runtime's staging buffer and costs about 28 us more
+// per build.  nullptr (and the pageable path) if the allocation fails.
+Control* pinned_ctl() {
+  static thread_local Control* pin = nullptr;
+  static thread_local bool tried = false;
+  if (!tried) {
+    tried = true;
+    if (hipHostMalloc(reinterpret_cast<void**>(&pin), sizeof(Control), hipHostMallocDefault) != hipSuccess) {
+      pin = nullptr;
+      (void)hipGetLastError();  // not left for the next launch check to report
+    }
+  }
+  return pin;
+}
+
 int read_ctl(const Build& b, HostCtl* h) {
-  Control c;
-  GB_TRY(hipMemcpyAsync(&c, at<Control>(b.ws, b.L.ctl), sizeof(Control), hipMemcpyDeviceToHost, b.s));
+  Control local;
+  Control* c = b.no_alloc ? nullptr : pinned_ctl();
+  if (!c) c = &local;
+  GB_TRY(hipMemcpyAsync(c, at<Control>(b.ws, b.L.ctl), sizeof(Control), hipMemcpyDeviceToHost, b.s));
   GB_TRY(hipStreamSynchronize(b.s));
-  h->npairs = c.npairs;
-  h->error = c.error;
-  h->cap_flag = c.cap_flag;
-  h->box_npairs = c.box_npairs;
+  h->npairs = c->npairs;
+  h->error = c->error;
+  h->cap_flag = c->cap_flag;
+  h->box_npairs = c->box_npairs;
   return GRID_OK;
 }
 
@@ -886,13 +910,18 @@ int grid_count(const float* verts_soa, uint32_t nverts, const uint32_t* tris, ui
   return st;
 }
 
-int grid_build(const float* verts_soa, uint32_t nverts, const uint32_t* tris, uint32_t ntris, const float lo[3],
-               const float hi[3], const uint32_t res[3], void* ws, size_t ws_bytes, grid_out* out, void* stream) {
+}  // extern "C"
+
+namespace {
+
+int build_plain(const float* verts_soa, uint32_t nverts, const uint32_t* tris, uint32_t ntris, const float lo[3],
+                const float hi[3], const uint32_t res[3], void* ws, size_t ws_bytes, grid_out* out, hipStream_t stream,
+                bool no_alloc) {
   if (!out || !out->ranges || (out->cap_pairs > 0 && (!out->cells || !out->objs))) return GRID_E_INVAL;
   Build b{};
-  int st = prepare_plain(b, verts_soa, nverts, tris, ntris, lo, hi, res, ws, ws_bytes, out->cap_pairs,
-                         static_cast<hipStream_t>(stream));
+  int st = prepare_plain(b, verts_soa, nverts, tris, ntris, lo, hi, res, ws, ws_bytes, out->cap_pairs, stream);
   if (st) return st;
+  b.no_alloc = no_alloc;
   b.gs.one.out_cells = out->cells;
   b.gs.one.out_objs = out->objs;
   b.gs.one.out_ranges = out->ranges;
@@ -925,6 +954,16 @@ int grid_build(const float* verts_soa, uint32_t nverts, const uint32_t* tris, ui
   if (h.npairs > 0xFFFFFFFFull) return GRID_E_OVERFLOW;
   if (h.npairs > cap) return GRID_E_CAPACITY;
   return GRID_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int grid_build(const float* verts_soa, uint32_t nverts, const uint32_t* tris, uint32_t ntris, const float lo[3],
+               const float hi[3], const uint32_t res[3], void* ws, size_t ws_bytes, grid_out* out, void* stream) {
+  return build_plain(verts_soa, nverts, tris, ntris, lo, hi, res, ws, ws_bytes, out, static_cast<hipStream_t>(stream),
+                     false);
 }
 
 int grid_build_culled(const float* verts_soa, uint32_t nverts, const uint32_t* tris, uint32_t ntris,
@@ -1028,7 +1067,8 @@ int grid_build_static(const float* verts_soa, uint32_t nverts, const uint32_t* t
   void* ws = nullptr;
   int st = static_scratch(&ws);
   if (st) return st;
-  return grid_build(verts_soa, nverts, tris, ntris, lo, hi, res, ws, GRID_STATIC_SCRATCH_BYTES, out, stream);
+  return build_plain(verts_soa, nverts, tris, ntris, lo, hi, res, ws, GRID_STATIC_SCRATCH_BYTES, out,
+                     static_cast<hipStream_t>(stream), true);
 }
 
 }  // extern "C"

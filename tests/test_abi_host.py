@@ -193,7 +193,8 @@ def test_sort_plan_is_valid_for_every_width(G, digit):
             assert sum(widths) == nbits
             assert all(1 <= w <= kbits for w in widths) and 8 <= kbits <= 11
             assert passes == min(4, -(-nbits // digit))
-            assert max(widths) - min(widths) <= 1          # balanced digits (25 bits: 9, 8, 8)
+            assert max(widths) - min(widths) <= 1          # balanced digits (25 bits: 8, 8, 9)
+            assert list(widths) == sorted(widths)          # the wider digits on top
             assert kbits == max(8, max(widths))
         assert G.sort_plan(0)[0] == 0
     finally:
