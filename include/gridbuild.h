@@ -297,6 +297,10 @@ int grid_scan_u32(const uint32_t *in, const uint32_t *flags, uint32_t *out, uint
  *   "sort_shape"      workgroup shape of radix passes that read arrays:
  *                     0 = 512 threads x 16 pairs, 1 = 256 x 16, 2 = 1024 x 8,
  *                     3 = 1024 x 16 (default), 4 = 1024 x 15
+ *   "small_tiles"     1 (default): a build (or batch) whose pair capacity would
+ *                     fill fewer 16384-pair tiles than the GPU has CUs runs
+ *                     those passes in 256 x 16 tiles whatever "sort_shape"
+ *                     says; 0: "sort_shape" always
  *   "per_object_pairs" 1: plain builds generate their pairs with one thread per
  *                     object, each writing all of its object's pairs (the
  *                     sorted-grid pair generation of the Related Work

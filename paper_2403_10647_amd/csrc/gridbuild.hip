@@ -155,6 +155,9 @@ int g_sort_shape = 3;  // radix passes from arrays: 0 = 512 x 16, 1 = 256 x 16, 
                        // 4 = 1024 x 15
 
 int sort_shape_tile(int shape) { return shape == 1 ? 4096 : shape == 3 ? 16384 : shape == 4 ? 15360 : 8192; }
+// 1: a build whose pairs would fill fewer 16384-pair tiles than the GPU has
+// CUs runs its passes from arrays in 256 x 16 tiles, whatever sort_shape says.
+int g_small_tiles = 1;
 
 Plan make_plan(uint32_t bits, int max_digit = -1) {
   Plan p{};
@@ -308,6 +311,7 @@ struct Build {
   uint64_t out_cap;      // culled builds: pairs the caller's outputs hold
   uint64_t layout_cap = ~uint64_t{0};  // pairs the workspace layout holds, checked by the plan
   bool no_alloc = false;  // the build may not allocate, not even host memory for its readback
+  int sort_shape = 3;     // tile shape of the radix passes from arrays (build_sort_shape)
 };
 
 template <bool B>
@@ -400,7 +404,17 @@ bool fused_first_pass(const Build& b) { return g_fused_expand != 0 && !b.culled;
 
 uint32_t pass_tile(const Build& b, uint32_t p) {
   return (fused_first_pass(b) && p == 0) ? static_cast<uint32_t>(kExpandTile)
-                                         : static_cast<uint32_t>(sort_shape_tile(g_sort_shape));
+                                         : static_cast<uint32_t>(sort_shape_tile(b.sort_shape));
+}
+
+// Radix tile shape for a build of at most cap_pairs pairs: the sort_shape
+// knob's, unless the pairs would fill fewer 16384-pair tiles than the GPU has
+// CUs.  Each tile's phases take about the same time whatever its size, so a
+// build with few tiles finishes sooner with more, smaller tiles spread over
+// more CUs (a 17K-pair pass: about 9 against 17 us).
+int build_sort_shape(uint64_t cap_pairs) {
+  if (g_small_tiles && ceil_div(cap_pairs, 16384) < static_cast<uint64_t>(device_cus())) return 1;
+  return g_sort_shape;
 }
 
 // The look-back words each radix pass of b's plan will use (kernels built for
@@ -583,8 +597,8 @@ void launch_onesweep(const SortPassArgs& a, uint32_t ntiles, hipStream_t s) {
 
 // A pass that reads arrays runs in the tile shape the sort_shape knob picks.
 template <int RB, int Snk, bool B>
-void launch_shaped(const SortPassArgs& a, uint32_t ntiles, hipStream_t s) {
-  switch (g_sort_shape) {
+void launch_shaped(const SortPassArgs& a, uint32_t ntiles, hipStream_t s, int shape) {
+  switch (shape) {
     case 1: launch_onesweep<256, 16, RB, kFromArrays, Snk, B>(a, ntiles, s); break;
     case 2: launch_onesweep<1024, 8, RB, kFromArrays, Snk, B>(a, ntiles, s); break;
     case 3: launch_onesweep<1024, 16, RB, kFromArrays, Snk, B>(a, ntiles, s); break;
@@ -594,28 +608,28 @@ void launch_shaped(const SortPassArgs& a, uint32_t ntiles, hipStream_t s) {
 }
 
 template <int RB, bool B>
-int launch_pass_rb(const SortPassArgs& a, bool regen, bool to_grids, uint32_t ntiles, hipStream_t s) {
+int launch_pass_rb(const SortPassArgs& a, bool regen, bool to_grids, uint32_t ntiles, hipStream_t s, int shape) {
   if (regen) {
     // regenerating passes read the expansion, whose tiles are kExpandTile pairs
     if (to_grids) launch_onesweep<kExpandBlock, kExpandK, RB, kFromExpansion, kToGrids, B>(a, ntiles, s);
     else launch_onesweep<kExpandBlock, kExpandK, RB, kFromExpansion, kToArrays, B>(a, ntiles, s);
   } else if (to_grids) {
-    if constexpr (B) launch_shaped<RB, kToGrids, B>(a, ntiles, s);
+    if constexpr (B) launch_shaped<RB, kToGrids, B>(a, ntiles, s, shape);
     else return GRID_E_INVAL;  // plain builds end in the caller's arrays
   } else {
-    launch_shaped<RB, kToArrays, B>(a, ntiles, s);
+    launch_shaped<RB, kToArrays, B>(a, ntiles, s, shape);
   }
   GB_LAUNCHED();
   return GRID_OK;
 }
 
 template <bool B>
-int launch_pass(SortPassArgs a, int rb, bool regen, bool to_grids, uint32_t ntiles, hipStream_t s) {
+int launch_pass(SortPassArgs a, int rb, bool regen, bool to_grids, uint32_t ntiles, hipStream_t s, int shape) {
   switch (rb) {
-    case 8: return launch_pass_rb<8, B>(a, regen, to_grids, ntiles, s);
-    case 9: return launch_pass_rb<9, B>(a, regen, to_grids, ntiles, s);
-    case 10: return launch_pass_rb<10, B>(a, regen, to_grids, ntiles, s);
-    case 11: return launch_pass_rb<11, B>(a, regen, to_grids, ntiles, s);
+    case 8: return launch_pass_rb<8, B>(a, regen, to_grids, ntiles, s, shape);
+    case 9: return launch_pass_rb<9, B>(a, regen, to_grids, ntiles, s, shape);
+    case 10: return launch_pass_rb<10, B>(a, regen, to_grids, ntiles, s, shape);
+    case 11: return launch_pass_rb<11, B>(a, regen, to_grids, ntiles, s, shape);
     default: return GRID_E_INVAL;
   }
 }
@@ -672,6 +686,7 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
   Control* ctl = at<Control>(b.ws, b.L.ctl);
   const uint32_t P = sp.passes;
   const bool fused = fused_first_pass(b);
+  b.sort_shape = build_sort_shape(npairs);  // before anything sizes or clears the passes' look-back words
   const uint32_t* in_k = nullptr;
   const uint32_t* in_v = nullptr;
   if (fused) {
@@ -731,7 +746,7 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
       const bool regen = fused && p == 0;
       const uint32_t pass_tiles = static_cast<uint32_t>(ceil_div(npairs, pass_tile(b, p)));
       TraceScope ts(b.s, regen ? "onesweep_expand" : (B && last) ? "onesweep_grids" : "onesweep");
-      int st = launch_pass<B>(a, pass_bits(sp.width[p]), regen, B && last, pass_tiles, b.s);
+      int st = launch_pass<B>(a, pass_bits(sp.width[p]), regen, B && last, pass_tiles, b.s, b.sort_shape);
       if (st) return st;
       GB_LAUNCHED();
       in_k = d.k;
@@ -1510,6 +1525,11 @@ int grid_tune_set(const char* key, int value) {
     g_sort_shape = value;
     return GRID_OK;
   }
+  if (std::strcmp(key, "small_tiles") == 0) {
+    if (value != 0 && value != 1) return GRID_E_INVAL;
+    g_small_tiles = value;
+    return GRID_OK;
+  }
   if (std::strcmp(key, "per_object_pairs") == 0) {
     if (value != 0 && value != 1) return GRID_E_INVAL;
     g_per_object_pairs = value;
@@ -1538,6 +1558,7 @@ int grid_tune_get(const char* key, int* value) {
   if (std::strcmp(key, "max_digit_bits") == 0) { *value = g_max_digit_bits; return GRID_OK; }
   if (std::strcmp(key, "fused_expand") == 0) { *value = g_fused_expand; return GRID_OK; }
   if (std::strcmp(key, "sort_shape") == 0) { *value = g_sort_shape; return GRID_OK; }
+  if (std::strcmp(key, "small_tiles") == 0) { *value = g_small_tiles; return GRID_OK; }
   if (std::strcmp(key, "per_object_pairs") == 0) { *value = g_per_object_pairs; return GRID_OK; }
   if (std::strcmp(key, "build_path") == 0) { *value = g_build_path; return GRID_OK; }
   if (std::strcmp(key, "last_path") == 0) { *value = g_last_path; return GRID_OK; }

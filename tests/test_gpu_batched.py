@@ -151,6 +151,7 @@ def test_batched_under_tuning(G, fused, digit, shape):
     G.tune_set("fused_expand", fused)
     G.tune_set("max_digit_bits", digit)
     G.tune_set("sort_shape", shape)
+    G.tune_set("small_tiles", 0)  # this batch would otherwise run the small-build shape
     try:
         batch = _uneven_batch()[:9]
         res = G.build_batched([G.GridInput.from_scene(s) for s in batch])
@@ -160,6 +161,7 @@ def test_batched_under_tuning(G, fused, digit, shape):
         G.tune_set("fused_expand", 0)
         G.tune_set("max_digit_bits", 9)
         G.tune_set("sort_shape", 3)
+        G.tune_set("small_tiles", 1)
 
 
 def test_batched_build_object_repeats(G):

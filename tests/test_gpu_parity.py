@@ -325,6 +325,7 @@ def test_build_under_every_tuning(G, fused, digit):
 @pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
 def test_build_under_every_sort_shape(G, shape):
     G.tune_set("sort_shape", shape)
+    G.tune_set("small_tiles", 0)  # these scenes would otherwise all run the small-build shape
     try:
         for name, n in [("mixed", 100_003), ("arch", 100_003)]:
             s = scenes.make_scene(name, ntris=n)
@@ -337,7 +338,25 @@ def test_build_under_every_sort_shape(G, shape):
             _check_build(G, s)
     finally:
         G.tune_set("sort_shape", 3)
+        G.tune_set("small_tiles", 1)
         G.tune_set("max_digit_bits", 9)
+
+
+def test_small_builds_take_small_tiles(G):
+    # a build with few pairs runs 4096-pair radix tiles whatever sort_shape says,
+    # and a large one the knob's shape; both equal the oracle
+    G.tune_set("sort_shape", 3)
+    for n in (4096, 30_000):
+        s = scenes.make_scene("arch", ntris=n)
+        s.name = f"arch-small-tiles-{n}"
+        _check_build(G, s)
+    G.tune_set("small_tiles", 0)
+    try:
+        s = scenes.make_scene("arch", ntris=30_000)
+        s.name = "arch-knob-tiles"
+        _check_build(G, s)
+    finally:
+        G.tune_set("small_tiles", 1)
 
 
 def test_plain_build_object_repeats(G):
