@@ -206,18 +206,59 @@ GB_DEV uint32_t merge_split(const uint32_t* cells, uint64_t npairs, uint64_t nev
   return static_cast<uint32_t>(lo);
 }
 
+// Plain builds: each workgroup first loads kSplitSamples evenly spaced cells
+// into LDS (one round of loads), and each search takes its first levels
+// there: it narrows [lo, hi] to the stretch between the two samples around
+// the answer, about npairs / kSplitSamples pairs, before it reads HBM.
+constexpr uint32_t kSplitSamples = 1024;
+
 template <int Block, bool Batched>
 __global__ __launch_bounds__(Block) void split_kernel(RangesArgs a) {
+  __shared__ uint32_t s_sample[Batched ? 1 : kSplitSamples];
   if (build_failed(a.ctl)) return;
   const uint32_t G = a.gs.ngrids;
   const uint32_t total = a.run[G].mtile_base;
+  if constexpr (!Batched) {
+    // sample k is the cell of pair k * npairs / kSplitSamples (< npairs)
+    const uint64_t np = a.run[0].npairs;
+    for (uint32_t k = threadIdx.x; k < kSplitSamples; k += Block)
+      s_sample[k] = np ? a.gs.one.out_cells[static_cast<uint64_t>(k) * np / kSplitSamples] : 0u;
+    __syncthreads();
+  }
   for (uint32_t b = blockIdx.x * Block + threadIdx.x; b < total; b += gridDim.x * Block) {
     const uint32_t g = Batched ? grid_of_mtile(a.run, G, b) : 0;
     const GridDev& gd = grid_at<Batched>(a.gs, g);
     const uint64_t ncell = static_cast<uint64_t>(gd.res[0]) * gd.res[1] * gd.res[2];
     const uint64_t d = static_cast<uint64_t>(b - a.run[g].mtile_base) * a.merge_tile;
-    a.splits[b] = merge_split(gd.out_cells, a.run[g].npairs, ncell + 1, d);
-    if constexpr (Batched) a.tile_grid[b] = g;
+    const uint64_t np = a.run[g].npairs;
+    if constexpr (Batched) {
+      a.splits[b] = merge_split(gd.out_cells, np, ncell + 1, d);
+      a.tile_grid[b] = g;
+    } else {
+      // the first sample k whose pair p_k = k * np / kSplitSamples already
+      // satisfies cells[p] + p + 1 >= d; the answer lies in (p_{k-1}, p_k]
+      // (k = kSplitSamples: in (p_{last}, np])
+      uint32_t kl = 0, kh = kSplitSamples;
+      while (kl < kh) {
+        const uint32_t km = (kl + kh) >> 1;
+        const uint64_t pm = static_cast<uint64_t>(km) * np / kSplitSamples;
+        if (static_cast<uint64_t>(s_sample[km]) + pm + 1 >= d) kh = km; else kl = km + 1;
+      }
+      const uint64_t L = kl ? static_cast<uint64_t>(kl - 1) * np / kSplitSamples + 1 : 0;
+      const uint64_t H = kl < kSplitSamples ? static_cast<uint64_t>(kl) * np / kSplitSamples : np;
+      // the search's own bounds, then the stretch (the answer is clamped to them)
+      const uint64_t lo0 = d > ncell + 1 ? d - (ncell + 1) : 0;
+      const uint64_t hi0 = d < np ? d : np;
+      uint64_t lo = L < hi0 ? L : hi0;
+      lo = lo > lo0 ? lo : lo0;
+      uint64_t hi = H > lo0 ? H : lo0;
+      hi = hi < hi0 ? hi : hi0;
+      while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (static_cast<uint64_t>(gd.out_cells[mid]) + mid + 1 >= d) hi = mid; else lo = mid + 1;
+      }
+      a.splits[b] = static_cast<uint32_t>(lo);
+    }
   }
 }
 
