@@ -344,11 +344,25 @@ def test_build_under_every_sort_shape(G, shape):
 
 def test_small_builds_take_small_tiles(G):
     # a build with few pairs runs 4096-pair radix tiles whatever sort_shape says,
-    # and a large one the knob's shape; both equal the oracle
+    # and a large one the knob's shape; both equal the oracle, also on either
+    # side of the switch (fewer 16384-pair tiles than the GPU has CUs)
     G.tune_set("sort_shape", 3)
     for n in (4096, 30_000):
         s = scenes.make_scene("arch", ntris=n)
         s.name = f"arch-small-tiles-{n}"
+        _check_build(G, s)
+    switch = torch.cuda.get_device_properties(0).multi_processor_count * 16384
+    below = above = None
+    for n in (800_000, 1_200_000, 1_400_000, 1_600_000, 1_800_000, 2_000_000, 2_600_000, 3_200_000):
+        s = scenes.make_scene("arch", ntris=n)
+        no, _ = G.count(G.GridInput.from_scene(s))
+        if no < switch:
+            below = s
+        elif above is None:
+            above = s
+    assert below is not None and above is not None
+    for s in (below, above):
+        s.name = f"arch-tiles-switch-{s.ntris}"
         _check_build(G, s)
     G.tune_set("small_tiles", 0)
     try:
