@@ -291,7 +291,8 @@ int grid_scan_u32(const uint32_t *in, const uint32_t *flags, uint32_t *out, uint
 /* Process-wide knobs (not thread-safe against concurrent builds; set them
  * before building).  Keys:
  *   "max_digit_bits"  widest radix digit a sort pass may use, 4..11 (default 9):
- *                     a b-bit key is sorted in ceil(b / max) passes of equal width
+ *                     a b-bit key is sorted in ceil(b / max) passes (at most 4)
+ *                     whose widths differ by at most one, the wider on top
  *   "fused_expand"    1: the first radix pass regenerates its keys from the
  *                     expansion instead of reading them (default 0)
  *   "sort_shape"      workgroup shape of radix passes that read arrays:
