@@ -302,6 +302,9 @@ int grid_scan_u32(const uint32_t *in, const uint32_t *flags, uint32_t *out, uint
  *                     fill fewer 16384-pair tiles than the GPU has CUs runs
  *                     those passes in 256 x 16 tiles whatever "sort_shape"
  *                     says; 0: "sort_shape" always
+ *   "wide_lookback"   0 (default): radix passes of fewer than 2^30 pairs (by
+ *                     capacity) keep 32-bit look-back words, larger ones 64-bit;
+ *                     1: 64-bit words always
  *   "per_object_pairs" 1: plain builds generate their pairs with one thread per
  *                     object, each writing all of its object's pairs (the
  *                     sorted-grid pair generation of the Related Work

@@ -169,38 +169,56 @@ GB_DEV uint64_t lookback_wave(uint64_t* status, uint32_t tile, uint64_t aggregat
   return excl;
 }
 
+// Look-back words of W bits (64, or 32 while every value fits in 30 bits):
+// the flag in the top two bits, the value below.  Half-width words halve
+// the look-back's stores and polls.
+template <typename W>
+GB_DEV void status_put(W* p, uint64_t flag, uint64_t value) {
+  constexpr int S = sizeof(W) * 8 - 2;
+  const W w = static_cast<W>((flag << S) | (value & ((uint64_t{1} << S) - 1)));
+  __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename W>
+GB_DEV W status_get(const W* p) {
+  return __hip_atomic_load(const_cast<W*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Look-back by one thread along status[(tile - 1) * stride + col], ....
 // The nearest predecessor usually holds its inclusive prefix already, so it
 // is read alone first; a chain of aggregates is then read four tiles per
 // round, one memory latency per four tiles.
-GB_DEV uint64_t lookback_thread(uint64_t* status, uint32_t stride, uint32_t col, uint32_t tile) {
+template <typename W>
+GB_DEV uint64_t lookback_thread(W* status, uint32_t stride, uint32_t col, uint32_t tile) {
   constexpr int kAhead = 4;
+  constexpr int S = sizeof(W) * 8 - 2;
+  constexpr W kMask = static_cast<W>((uint64_t{1} << S) - 1);
   uint64_t excl = 0;
   int64_t j = static_cast<int64_t>(tile) - 1;
   if (j < 0) return 0;
   {
-    const uint64_t s = status_load(status + static_cast<uint64_t>(j) * stride + col);
-    const uint64_t flag = s >> 62;
-    if (flag == kFlagPrefix) return s & kValueMask;
+    const W s = status_get(status + static_cast<uint64_t>(j) * stride + col);
+    const W flag = s >> S;
+    if (flag == kFlagPrefix) return s & kMask;
     if (flag == kFlagAggregate) {
-      excl = s & kValueMask;
+      excl = s & kMask;
       --j;
     }
   }
   while (j >= 0) {
-    uint64_t s[kAhead];
+    W s[kAhead];
 #pragma unroll
     for (int u = 0; u < kAhead; ++u)
-      s[u] = j - u >= 0 ? status_load(status + static_cast<uint64_t>(j - u) * stride + col) : (kFlagPrefix << 62);
+      s[u] = j - u >= 0 ? status_get(status + static_cast<uint64_t>(j - u) * stride + col)
+                        : static_cast<W>(static_cast<W>(kFlagPrefix) << S);
     bool done = false, stalled = false;
 #pragma unroll
     for (int u = 0; u < kAhead; ++u) {
       if (done || stalled) continue;
-      const uint64_t flag = s[u] >> 62;
+      const W flag = s[u] >> S;
       if (flag == kFlagInvalid) {
         stalled = true;
       } else {
-        excl += s[u] & kValueMask;
+        excl += s[u] & kMask;
         --j;
         if (flag == kFlagPrefix) done = true;
       }

@@ -589,9 +589,17 @@ int launch_cull(Build& b, uint32_t* cells, uint32_t* objs, uint64_t dest_cap, ui
 // 8-bit pass of a 25-bit key does not pay for 9-bit ranking.
 int pass_bits(uint32_t width) { return std::max(8, static_cast<int>(width)); }
 
+// Passes that read arrays come in two builds, by look-back word width.
 template <int Blk, int K, int RB, int Src, int Snk, bool B>
 void launch_onesweep(const SortPassArgs& a, uint32_t ntiles, hipStream_t s) {
-  auto k = onesweep_kernel<Blk, K, RB, Src, Snk, B>;
+  if constexpr (Src == kFromArrays) {
+    if (a.narrow) {
+      auto k = onesweep_kernel<Blk, K, RB, Src, Snk, B, true>;
+      k<<<resident_blocks(k, Blk, ntiles), Blk, 0, s>>>(a);
+      return;
+    }
+  }
+  auto k = onesweep_kernel<Blk, K, RB, Src, Snk, B, false>;
   k<<<resident_blocks(k, Blk, ntiles), Blk, 0, s>>>(a);
 }
 
@@ -675,6 +683,13 @@ int launch_sink(Build& b) {
   return GRID_OK;
 }
 
+// Radix passes of fewer pairs than this use 32-bit look-back words (a 30-bit
+// value each): half the stores and polls of 64-bit words.  The wide_lookback
+// knob keeps 64-bit words for every build.
+constexpr uint64_t kNarrowLimit = uint64_t{1} << 30;
+int g_wide_lookback = 0;
+uint32_t narrow_words(uint64_t max_pairs) { return !g_wide_lookback && max_pairs < kNarrowLimit ? 1u : 0u; }
+
 template <int RB, bool B>
 int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t npairs) {
   const SortPlan& sp = b.plan.sp;
@@ -732,6 +747,7 @@ int launch_sort_rb(Build& b, uint32_t* out_cells, uint32_t* out_objs, uint64_t n
       a.status = at<uint64_t>(b.ws, b.L.sort_status) + static_cast<uint64_t>(p) * b.L.nsort_tiles_cap * (1u << RB);
       a.n = npairs;
       a.n_from_ctl = 1;  // the pass reads NO from the control block
+      a.narrow = narrow_words(npairs);  // NO <= the capacity npairs
       a.shift = sp.shift[p];
       a.width = sp.width[p];
       a.counter = kCtrSort0 + p;
@@ -1355,14 +1371,19 @@ int sort_arrays_rb(uint32_t* keys, uint32_t* vals, uint32_t* ka, uint32_t* va, u
     a.hist_stride = 0;
     a.status = at<uint64_t>(ws, L.status) + p * stride;
     a.n = n;
+    a.narrow = narrow_words(n);
     a.n_from_ctl = 0;
     a.shift = plan.sp.shift[p];
     a.width = plan.sp.width[p];
     a.counter = kCtrSort0 + p;
     a.ctl = ctl;
     TraceScope ts(s, "onesweep");
-    onesweep_kernel<kSortBlock, kSortK, RB, kFromArrays, kToArrays, false>
-        <<<persistent_blocks(L.ntiles, 2), kSortBlock, 0, s>>>(a);
+    if (a.narrow)
+      onesweep_kernel<kSortBlock, kSortK, RB, kFromArrays, kToArrays, false, true>
+          <<<persistent_blocks(L.ntiles, 2), kSortBlock, 0, s>>>(a);
+    else
+      onesweep_kernel<kSortBlock, kSortK, RB, kFromArrays, kToArrays, false, false>
+          <<<persistent_blocks(L.ntiles, 2), kSortBlock, 0, s>>>(a);
     GB_LAUNCHED();
     std::swap(src_k, dst_k);
     std::swap(src_v, dst_v);
@@ -1530,6 +1551,11 @@ int grid_tune_set(const char* key, int value) {
     g_small_tiles = value;
     return GRID_OK;
   }
+  if (std::strcmp(key, "wide_lookback") == 0) {
+    if (value != 0 && value != 1) return GRID_E_INVAL;
+    g_wide_lookback = value;
+    return GRID_OK;
+  }
   if (std::strcmp(key, "per_object_pairs") == 0) {
     if (value != 0 && value != 1) return GRID_E_INVAL;
     g_per_object_pairs = value;
@@ -1559,6 +1585,7 @@ int grid_tune_get(const char* key, int* value) {
   if (std::strcmp(key, "fused_expand") == 0) { *value = g_fused_expand; return GRID_OK; }
   if (std::strcmp(key, "sort_shape") == 0) { *value = g_sort_shape; return GRID_OK; }
   if (std::strcmp(key, "small_tiles") == 0) { *value = g_small_tiles; return GRID_OK; }
+  if (std::strcmp(key, "wide_lookback") == 0) { *value = g_wide_lookback; return GRID_OK; }
   if (std::strcmp(key, "per_object_pairs") == 0) { *value = g_per_object_pairs; return GRID_OK; }
   if (std::strcmp(key, "build_path") == 0) { *value = g_build_path; return GRID_OK; }
   if (std::strcmp(key, "last_path") == 0) { *value = g_last_path; return GRID_OK; }

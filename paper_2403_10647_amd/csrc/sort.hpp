@@ -5,6 +5,8 @@
 // buffer so each digit's run is written contiguously.
 #pragma once
 
+#include <type_traits>
+
 #include "ranges.hpp"
 
 namespace gb {
@@ -20,6 +22,7 @@ struct SortPassArgs {
   ExpandArgs ex;            // kFromExpansion (and grid table for kToGrids)
   const uint32_t* hist;     // global digit histogram of this pass [radix]
   uint64_t* status;         // [ntiles][radix] look-back words (zeroed)
+  uint32_t narrow;          // 1: launch the 32-bit look-back word kernel (every pass value below 2^30)
   uint64_t n;               // pairs, when not read from the control block
   uint32_t n_from_ctl;      // 1: n = ctl->npairs
   uint32_t hist_copies;     // the pass's digit histogram is the sum of this many copies ...
@@ -45,8 +48,12 @@ constexpr int onesweep_waves(int Block, int K, int RB, int Source) {
          : 4;
 }
 
-template <int Block, int K, int RB, int Source, int Sink, bool Batched>
+// Narrow: 32-bit look-back words (flag and a 30-bit value), for passes of
+// fewer than 2^30 pairs; 64-bit words otherwise.
+template <int Block, int K, int RB, int Source, int Sink, bool Batched, bool Narrow = false>
 __global__ __launch_bounds__(Block, onesweep_waves(Block, K, RB, Source)) void onesweep_kernel(SortPassArgs a) {
+  using SW = typename std::conditional<Narrow, uint32_t, uint64_t>::type;
+  SW* const status = reinterpret_cast<SW*>(a.status);
   constexpr int N = Block * K;
   constexpr int R = 1 << RB;
   constexpr int W = Block / kWave;
@@ -167,7 +174,7 @@ __global__ __launch_bounds__(Block, onesweep_waves(Block, K, RB, Source)) void o
         if (tile == 0) {
           // tile 0 starts each digit at the digit's global offset
         } else {
-          status_store(a.status + static_cast<uint64_t>(tile) * R + d, kFlagAggregate, run);
+          status_put(status + static_cast<uint64_t>(tile) * R + d, kFlagAggregate, run);
         }
       }
       dcount[j] = run;
@@ -222,7 +229,7 @@ __global__ __launch_bounds__(Block, onesweep_waves(Block, K, RB, Source)) void o
       for (int j = 0; j < DPT; ++j) {
         const uint32_t d = tid * DPT + j;
         if (d < static_cast<uint32_t>(R)) {
-          status_store(a.status + d, kFlagPrefix, static_cast<uint64_t>(hex) + dcount[j]);
+          status_put(status + d, kFlagPrefix, static_cast<uint64_t>(hex) + dcount[j]);
           s_dst[d] = hex - texcl;
         }
         hex += hv[j];
@@ -234,8 +241,8 @@ __global__ __launch_bounds__(Block, onesweep_waves(Block, K, RB, Source)) void o
       for (int j = 0; j < DPT; ++j) {
         const uint32_t d = tid * DPT + j;
         if (d < static_cast<uint32_t>(R)) {
-          const uint64_t ex = lookback_thread(a.status, R, d, tile);
-          status_store(a.status + static_cast<uint64_t>(tile) * R + d, kFlagPrefix, ex + dcount[j]);
+          const uint64_t ex = lookback_thread(status, R, d, tile);
+          status_put(status + static_cast<uint64_t>(tile) * R + d, kFlagPrefix, ex + dcount[j]);
           s_dst[d] = static_cast<uint32_t>(ex) - texcl;
         }
         texcl += dcount[j];

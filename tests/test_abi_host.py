@@ -212,8 +212,11 @@ def test_tune_rejects_bad_values(G):
         G.tune_set("per_object_pairs", 2)
     with pytest.raises(G.GridError):
         G.tune_set("small_tiles", 2)
+    with pytest.raises(G.GridError):
+        G.tune_set("wide_lookback", 2)
     assert G.tune_get("max_digit_bits") == 9 and G.tune_get("fused_expand") in (0, 1)
     assert G.tune_get("per_object_pairs") == 0 and G.tune_get("small_tiles") == 1
+    assert G.tune_get("wide_lookback") == 0
 
 
 def test_workspace_size_follows_the_digit_width(G):

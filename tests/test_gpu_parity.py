@@ -373,6 +373,33 @@ def test_small_builds_take_small_tiles(G):
         G.tune_set("small_tiles", 1)
 
 
+@pytest.mark.parametrize("shape", [3, 4])
+def test_build_with_wide_lookback_words(G, shape):
+    # radix passes under 2^30 pairs keep 32-bit look-back words; the 64-bit
+    # words of larger builds give the same grid
+    G.tune_set("wide_lookback", 1)
+    G.tune_set("sort_shape", shape)
+    G.tune_set("small_tiles", 0)
+    try:
+        for name, n in [("mixed", 100_003), ("arch", 300_000)]:
+            s = scenes.make_scene(name, ntris=n)
+            s.name = f"{name}-wide-lookback-shape{shape}"
+            _check_build(G, s)
+        batch = scenes.make_batch(5, ngrids=7, sizes=np.asarray([3000, 0, 40_000, 1, 900, 12_000, 5]))
+        for sc in batch:
+            if sc.ntris == 0:
+                sc.lo, sc.hi, sc.res = np.zeros(3, np.float32), np.ones(3, np.float32), np.asarray([3, 2, 5], np.uint32)
+        res = G.build_batched([G.GridInput.from_scene(sc) for sc in batch])
+        for r, sc in zip(res, batch):
+            c, o, rg = r.numpy()
+            oc, oo, orr = oracle.build_scene(sc)
+            assert np.array_equal(c, oc) and np.array_equal(o, oo) and np.array_equal(rg, orr), sc.name
+    finally:
+        G.tune_set("wide_lookback", 0)
+        G.tune_set("sort_shape", 3)
+        G.tune_set("small_tiles", 1)
+
+
 def test_plain_build_object_repeats(G):
     # the marshalled-once build equals G.build and the oracle, call after call
     s = scenes.make_scene("mixed", ntris=30_000)
