@@ -411,7 +411,7 @@ uint32_t pass_tile(const Build& b, uint32_t p) {
 // knob's, unless the pairs would fill fewer 16384-pair tiles than the GPU has
 // CUs.  Each tile's phases take about the same time whatever its size, so a
 // build with few tiles finishes sooner with more, smaller tiles spread over
-// more CUs (a 17K-pair pass: about 9 against 17 us).
+// more CUs (a 17K-pair pass: 15 against 20 us).
 int build_sort_shape(uint64_t cap_pairs) {
   if (g_small_tiles && ceil_div(cap_pairs, 16384) < static_cast<uint64_t>(device_cus())) return 1;
   return g_sort_shape;
